@@ -1,0 +1,232 @@
+"""Whole-step pins of the oracle: special cases whose answer the paper or
+textbook fluid mechanics fixes (Sec. 2.2, 3.1).  CPU only, small grids."""
+import numpy as np
+import pytest
+from scipy import optimize, special
+
+import oracle as O
+from paper_1512_01977_amd import inputs
+
+CS_TC = None
+
+
+def cs_params(nz, nr, t=0.8, **kw):
+    global CS_TC
+    if CS_TC is None:
+        CS_TC = O.critical(O.Params(nz=4, nr=4, eos=O.EOS_CS))[1]
+    kw.setdefault("tau", 1.0)
+    return O.Params(nz=nz, nr=nr, eos=O.EOS_CS, T=t * CS_TC, **kw)
+
+
+def ideal(nz, nr, **kw):
+    return O.Params(nz=nz, nr=nr, eos=O.EOS_IDEAL, **kw)
+
+
+def radii(nr):
+    return np.arange(nr) + 0.5
+
+
+# --------------------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("bc_top", [O.TOP_FREE_SLIP, O.TOP_NO_SLIP])
+def test_uniform_rest_state_is_stationary(bc_top):
+    # No gradients, no velocity: F_K = F_axis = 0 and h_i = 0, walls reflect a rest state onto itself.
+    p = cs_params(12, 9, t=0.8, A=-0.152, bc_top=bc_top)
+    rv, rl, _ = O.coexistence(p)
+    for rho0 in (rv, rl):
+        f = O.init(p, np.full((9, 12), rho0))
+        O.step(p, f, 30)
+        rho, uz, ur = O.moments(p, f)
+        assert np.abs(rho - rho0).max() <= 1e-15 * rho0 * 10
+        assert np.abs(uz).max() <= 1e-16 and np.abs(ur).max() <= 1e-16
+
+
+def _droplet(p, R=10.0, eps=0.0, seed=4):
+    rv, rl, _ = O.coexistence(p)
+    return inputs.droplet(p.nz, p.nr, rv, rl, R, eps=eps, noise=1e-4, seed=seed)
+
+
+def test_2d_mode_conserves_mass_exactly():
+    p = cs_params(48, 24, axisym=0)
+    f = O.init(p, _droplet(p))
+    m0 = f.sum()
+    O.step(p, f, 200)
+    assert abs(f.sum() - m0) <= 1e-13 * m0
+
+
+def test_axisymmetric_mass_source_per_step():
+    # BGK and the exact-difference shift conserve mass, streaming only permutes populations,
+    # so sum_x rho^{n+1} - sum_x rho^n = sum_x sum_i h_i = -sum_x rho u_r / r (eq. masscylinderical).
+    p = cs_params(48, 24, axisym=1)
+    f = O.init(p, _droplet(p, eps=0.1))
+    O.step(p, f, 40)
+    rho, uz, ur = O.moments(p, f)
+    s0 = f.sum()
+    src = -(rho * ur / radii(p.nr)[:, None]).sum()
+    O.step(p, f, 1)
+    assert abs(src) > 1e-8 * s0
+    assert (f.sum() - s0) == pytest.approx(src, rel=1e-9, abs=1e-14 * s0)
+
+
+@pytest.mark.parametrize("axisym", [0, 1])
+def test_body_force_adds_momentum(axisym):
+    # Exact-difference forcing adds F dt to the momentum of every node (Sec. 2.3); specular walls
+    # and periodic z conserve z-momentum, so sum j_z grows by N g_z per step.
+    g = 1e-6
+    p = ideal(10, 6, gz=g, axisym=axisym)
+    f = O.init(p, np.full((6, 10), 0.9))
+    O.step(p, f, 25)
+    jz = (O.CZ[:, None, None] * f).sum(0)
+    assert np.allclose(jz, 25 * g, rtol=1e-10)
+
+
+def test_z_mirror_symmetry_is_preserved():
+    p = cs_params(64, 24, axisym=1)
+    rv, rl, _ = O.coexistence(p)
+    rho0 = inputs.droplet(64, 24, rv, rl, 9.0, zc=32.0, eps=0.15)
+    f = O.init(p, rho0)
+    O.step(p, f, 150)
+    rho, uz, ur = O.moments(p, f)
+    mirror = (-np.arange(64)) % 64            # z -> 64 - z about z_c = 32
+    assert np.abs(rho - rho[:, mirror]).max() < 1e-12
+    assert np.abs(uz + uz[:, mirror]).max() < 1e-12
+    assert np.abs(ur - ur[:, mirror]).max() < 1e-12
+    assert np.abs(ur).max() > 1e-5            # the state is not trivially at rest
+
+
+def test_eos_domain_error_path():
+    p = cs_params(8, 8, t=0.485)
+    with pytest.raises(O.OracleError) as e:
+        O.init(p, np.full((8, 8), 0.6))       # psi is not real above about 0.557
+    assert e.value.code == -4
+    with pytest.raises(O.OracleError):
+        O.init(p, np.full((8, 8), np.nan))
+    with pytest.raises(O.OracleError) as e:
+        O.init(cs_params(8, 8, tau=0.5), np.full((8, 8), 0.1))
+    assert e.value.code == -1
+    with pytest.raises(O.OracleError):
+        O.init(cs_params(8, 3), np.full((3, 8), 0.1))
+
+
+# --------------------------------------------------------------------------- flows with closed forms
+
+def test_shear_wave_decay_rate():
+    # Ideal EOS, 2-D: u_z = U cos(k r) decays as exp(-nu k^2 t), nu = (tau - 1/2)/3.
+    nz, nr, tau = 4, 32, 0.8
+    k = np.pi / nr
+    p = ideal(nz, nr, tau=tau, axisym=0)
+    u0 = 1e-4 * np.cos(k * radii(nr))
+    f = O.init(p, np.ones((nr, nz)), uz0=np.repeat(u0[:, None], nz, 1))
+    t = 400
+    O.step(p, f, t)
+    _, uz, _ = O.moments(p, f)
+    amp = (uz[:, 0] * np.cos(k * radii(nr))).sum() / (np.cos(k * radii(nr)) ** 2).sum()
+    nu = (tau - 0.5) / 3
+    assert amp / 1e-4 == pytest.approx(np.exp(-nu * k * k * t), rel=2e-3)
+
+
+def test_hagen_poiseuille_profile():
+    # Ideal EOS, axisymmetric, no-slip wall at r = nr, uniform force density g:
+    # u_z(r) = g (R^2 - r^2) / (4 mu).  A plane channel would give (R^2 - r^2)/(2 mu), so the
+    # 1/r viscous term of H_z (Sec. 2.2) is what fixes the factor 4.
+    nr, tau, g, rho0 = 16, 1.0, 1e-7, 1.0
+    p = ideal(1, nr, tau=tau, axisym=1, bc_top=O.TOP_NO_SLIP, gz=g)
+    f = O.init(p, np.full((nr, 1), rho0))
+    O.step(p, f, 12000)
+    _, uz, ur = O.moments(p, f)
+    mu = rho0 * (tau - 0.5) / 3
+    exact = g * (nr ** 2 - radii(nr) ** 2) / (4 * mu)
+    assert np.abs(uz[:, 0] - exact).max() < 0.01 * exact.max()
+    assert np.abs(ur).max() < 1e-3 * exact.max()
+
+
+def _mode_history(p, rho0, shape, steps):
+    f = O.init(p, rho0)
+    amps = []
+    for _ in range(steps):
+        O.step(p, f, 1)
+        rho = f.sum(0)
+        amps.append((rho - 1.0).ravel() @ shape.ravel() / (shape.ravel() @ shape.ravel()))
+    return np.array(amps)
+
+
+def _fit_damped(a):
+    t = np.arange(1, len(a) + 1, dtype=float)
+    model = lambda t, A, g, w, ph: A * np.exp(-g * t) * np.cos(w * t + ph)
+    spec = np.abs(np.fft.rfft(a - a.mean()))
+    w0 = 2 * np.pi * np.argmax(spec[1:]) / len(a) + 2 * np.pi / len(a)
+    popt, _ = optimize.curve_fit(model, t, a, p0=[a[0], 1e-3, w0, 0.0], maxfev=20000)
+    return popt[1], popt[2]
+
+
+@pytest.mark.parametrize("printed", [0, 1])
+def test_bessel_mode_decays_like_plane_wave(printed):
+    # A 3-D isotropic fluid has one frequency and one attenuation per |k|: a J_0(k r) standing
+    # density mode of the axisymmetric model (free-slip wall at a zero of J_1) must match a
+    # cos(k z) mode of the 2-D model.  The printed +u_r/r in H_r breaks the attenuation.
+    tau = 0.9
+    j11 = special.jn_zeros(1, 1)[0]
+    nr = 61
+    k = j11 / nr
+    pa = ideal(1, nr, tau=tau, axisym=1, hr_printed_sign=printed)
+    shape_a = special.j0(k * radii(nr))[:, None]
+    try:
+        ga, wa = _fit_damped(_mode_history(pa, 1.0 + 1e-4 * shape_a, shape_a, 700))
+    except O.OracleError:
+        assert printed == 1        # the printed sign is unstable at the axis
+        return
+    nz = int(round(2 * np.pi / k))
+    pz = ideal(nz, 4, tau=tau, axisym=0)
+    shape_z = np.repeat(np.cos(2 * np.pi * np.arange(nz) / nz)[None, :], 4, 0)
+    gz, wz = _fit_damped(_mode_history(pz, 1.0 + 1e-4 * shape_z, shape_z, 700))
+    kz = 2 * np.pi / nz
+    # same |k| up to the rounding of nz: compare rates scaled by k^2 and frequencies by k
+    assert wa / k == pytest.approx(wz / kz, rel=5e-3)
+    match = abs((ga / k ** 2) / (gz / kz ** 2) - 1.0) < 0.05
+    assert match == (printed == 0), (ga / k ** 2, gz / kz ** 2)
+
+
+# --------------------------------------------------------------------------- multiphase validation
+
+def _static_dp_r(p, R, steps):
+    """Laplace pressure difference times the volume-equivalent radius of a static droplet."""
+    rv, rl, _ = O.coexistence(p)
+    f = O.init(p, inputs.droplet(p.nz, p.nr, rv, rl, R, noise=1e-4, seed=1))
+    O.step(p, f, steps)
+    rho, _, _ = O.moments(p, f)
+    zc = p.nz / 2
+    dp = O.laplace(p, f, zc, R / 2, R + 12)
+    Z, Rr = np.meshgrid(np.arange(p.nz) - zc, radii(p.nr))
+    d = np.hypot(Z, Rr)
+    rin, rout = rho[d < R / 2].mean(), rho[d > R + 12].mean()
+    frac = (rho - rout) / (rin - rout)
+    if p.axisym:
+        vol = (2 * np.pi * Rr * frac).sum()
+        req = (3 * vol / (4 * np.pi)) ** (1 / 3)
+    else:
+        req = np.sqrt(2 * frac.sum() / np.pi)   # the half-plane holds half of the 2-D drop
+    return dp * req
+
+
+@pytest.mark.slow
+def test_static_droplet_laplace_scaling():
+    # Sec. 3.1: the pressure jump of a static droplet scales as 1/R (Young-Laplace), so dp R_eq
+    # is the same for every radius.
+    vals = np.array([_static_dp_r(cs_params(96, 48, t=0.8, tau=1.0, axisym=1), R, 2500)
+                     for R in (12.0, 16.0, 20.0)])
+    assert vals.min() > 0
+    assert vals.std() / vals.mean() < 0.03, vals
+
+
+@pytest.mark.slow
+def test_static_droplet_axisymmetric_vs_2d():
+    # Table 1 compares sigma = dp R_0 (eq. laplacepressure) of the axisymmetric model, whose
+    # F_axis carries the thermodynamic c_k^4 (Sec. 2.3), with a 2-D run; the paper finds them
+    # within a few per cent (1.3 % at R_0 = 150).  Here R ~ 17 with a five-node interface.
+    # With the lattice c_s^4 instead, F_axis adds the azimuthal curvature and the axisymmetric
+    # jump rises well above the 2-D one, toward the sphere's 2 sigma / R.
+    ax_ck = _static_dp_r(cs_params(96, 48, t=0.8, tau=1.0, axisym=1, faxis_sound=0), 16.0, 2500)
+    ax_cs = _static_dp_r(cs_params(96, 48, t=0.8, tau=1.0, axisym=1, faxis_sound=1), 16.0, 2500)
+    two_d = _static_dp_r(cs_params(96, 48, t=0.8, tau=1.0, axisym=0), 16.0, 2500)
+    assert ax_ck == pytest.approx(two_d, rel=0.10)
+    assert 1.3 < ax_cs / two_d < 2.05
