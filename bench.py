@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the axisymmetric multiphase LBM step on one MI355X.
+
+A step is one time step of the whole method over every node of the workload:
+pull streaming, moments, FP64 EOS and pseudopotential, Kupershtokh force with the
+exact-difference shift, axisymmetric force correction and source terms, BGK.
+Default workload: the 256-member droplet ensemble in FP32 storage, all members in
+one launch per step, replayed as hipGraph chunks of 100 steps.  The same line
+also reports the single large domain (16384 x 8192) in FP32 and in FP64.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+# per node and step: read the 9 populations once and write them once
+BYTES_PER_NODE = {"f32": 2 * 9 * 4, "f64": 2 * 9 * 8}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("lbm_kernels.hip", "lbm_axi_internal.h"):
+        with open(os.path.join(ROOT, "paper_1512_01977_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, dtype: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when
+    there is none for this workload or the kernel source changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    rec = data.get(f"{workload}:{dtype}")
+    if not rec or rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_form(wl, steps, warmup, graph_chunk, tune, label):
+    import torch
+    from paper_1512_01977_amd import lbm, tuning
+
+    dtype = "f32" if wl.precision == lbm.PREC_FP32 else "f64"
+    log(f"[bench] {label}: {wl.name} {dtype}, {wl.nodes} nodes, {len(wl.params)} instance(s)")
+    t0 = time.perf_counter()
+    sim = lbm.LbmAxi(wl.params if len(wl.params) > 1 else wl.params[0],
+                     wl.rho0 if len(wl.params) > 1 else wl.rho0[0], precision=wl.precision)
+    log(f"[bench] {label}: state on the device in {time.perf_counter() - t0:.1f} s")
+    launch = tuning.choose_launch(sim, wl, tune=tune, log=log)
+    log(f"[bench] {label}: launch {launch}")
+    if graph_chunk:
+        sim.set_graph_chunk(graph_chunk)
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev_ms = sim.step_timed(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.sync()
+    mass = float(sim.mass().sum())
+    sim.close()
+    nodes = wl.nodes
+    per_launch_s = ev_ms / 1e3 / steps
+    achieved = BYTES_PER_NODE[dtype] * nodes / per_launch_s / 1e9
+    traffic = measured_traffic(wl.name, dtype)
+    res = {
+        "workload": wl.name, "dtype": dtype, "nodes": nodes, "steps": steps,
+        "ms_per_step": wall * 1e3 / steps, "kernel_ms_per_step": ev_ms / steps,
+        "MLUPS": nodes * steps / wall / 1e6,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic},
+        "launch": launch, "mass_after": mass,
+    }
+    log(f"[bench] {label}: {res['MLUPS']:.0f} MLUPS, {achieved:.0f} GB/s algorithmic "
+        f"({100 * achieved / HBM_PEAK_GBPS:.1f}% of HBM peak)")
+    return res
+
+
+def cpu_baseline(wl, budget_s=15.0):
+    """The CPU oracle, as it is, on a bounded sample of the same workload: the first
+    members of the workload (or a band of rows of a single domain) for a few steps."""
+    import numpy as np
+
+    import oracle as O
+    from paper_1512_01977_amd import lbm
+
+    def oparams(p):
+        return O.Params(nz=p.nz, nr=p.nr, tau=p.tau, eos=p.eos, T=p.T, eos_a=p.eos_a,
+                        eos_b=p.eos_b, eos_R=p.eos_R, lam=p.lam, A=p.A, axisym=p.axisym,
+                        faxis_sound=p.faxis_sound, bc_top=p.bc_top, gz=p.gz)
+
+    members = []
+    if len(wl.params) > 1:
+        for p, r in zip(wl.params, wl.rho0):
+            members.append((oparams(p), r))
+            if sum(q.nz * q.nr for q, _ in members) >= 2_000_000:
+                break
+    else:
+        p = wl.params[0]
+        rows = max(8, min(p.nr, 2_000_000 // p.nz))
+        q = oparams(p)
+        q.nr = rows
+        members.append((q, np.ascontiguousarray(wl.rho0[0][:rows])))
+    states = [(q, O.init(q, r)) for q, r in members]
+    nodes = sum(q.nz * q.nr for q, _ in states)
+    t0 = time.perf_counter()
+    for q, f in states:
+        O.step(q, f, 1)
+    per_step = time.perf_counter() - t0
+    steps = max(1, int(budget_s / max(per_step, 1e-6)))
+    t0 = time.perf_counter()
+    for q, f in states:
+        O.step(q, f, steps)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{len(states)} member(s) of {wl.name} ({nodes} nodes) for {steps} steps, "
+                      f"FP64 C oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="batch", choices=["batch", "large", "wave", "mode2", "static"])
+    ap.add_argument("--precision", default=None, choices=["fp32", "fp64"])
+    ap.add_argument("--forms", default="all", choices=["all", "main"],
+                    help="all: also time the large single domain in FP32 and FP64")
+    ap.add_argument("--graph-chunk", type=int, default=100)
+    ap.add_argument("--no-tune", action="store_true", help="use the cached or default launch shape")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the method's single-GPU kernel is what this "
+              "build provides (no multi-GPU path); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU (the HIP library has no CPU path).", file=sys.stderr)
+        sys.exit(2)
+    from paper_1512_01977_amd import lbm, workloads
+
+    prec = {"fp32": lbm.PREC_FP32, "fp64": lbm.PREC_FP64}
+    default_prec = {"batch": "fp32", "large": "fp32", "wave": "fp32", "mode2": "fp32",
+                    "static": "fp64"}
+    main_prec = prec[args.precision or default_prec[args.workload]]
+    t_all = time.perf_counter()
+    wl = workloads.REGISTRY[args.workload](precision=main_prec)
+    chunk = args.graph_chunk if args.steps >= args.graph_chunk else 0
+    main_res = run_form(wl, args.steps, args.warmup, chunk, not args.no_tune, "main")
+
+    forms = [main_res]
+    if args.forms == "all":
+        for w_name, p_name, steps in (("large", "fp32", 100), ("large", "fp64", 60)):
+            if w_name == args.workload and prec[p_name] == main_prec:
+                continue
+            w = workloads.REGISTRY[w_name](precision=prec[p_name])
+            forms.append(run_form(w, steps, 4, 0, not args.no_tune, f"{w_name}-{p_name}"))
+            del w
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline: timing the oracle on a bounded sample")
+        cpu = cpu_baseline(wl)
+        log(f"[bench] cpu baseline: {cpu['value']:.2f} MLUPS on {cpu['cores']} threads")
+
+    out = {
+        "metric": "MLUPS (million lattice-node updates per second) + achieved HBM GB/s",
+        "value": main_res["MLUPS"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": main_res["dtype"],
+        "data": "synthetic (seeded initial conditions of the paper's validation set-ups)",
+        "config": {"workload": wl.name, "nodes": wl.nodes, "instances": len(wl.params),
+                   "graph_chunk": chunk, "launch": main_res["launch"]},
+        "roofline": main_res["roofline"],
+        "cpu_baseline": cpu,
+        "forms": [{k: f[k] for k in ("workload", "dtype", "MLUPS", "ms_per_step",
+                                     "kernel_ms_per_step", "roofline", "launch")} for f in forms],
+        "wall_s": time.perf_counter() - t_all,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

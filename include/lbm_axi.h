@@ -1,0 +1,182 @@
+/*
+ * lbm_axi.h -- C ABI of the MI355X axisymmetric multiphase lattice Boltzmann library.
+ *
+ * The library advances the D2Q9 BGK lattice Boltzmann method on the (z, r)
+ * half-plane of Reijers, Gelderblom and Toschi (arXiv:1512.01977):
+ *   - pull streaming with mid-grid specular reflection at the axis r = 0 and a
+ *     free-slip (specular) or no-slip (half-way bounce-back) wall at r = nr,
+ *     periodic in z (Sec. 3.1-3.3);
+ *   - density and momentum moments, physical velocity u = (j + F/2)/rho (Sec. 2.1);
+ *   - a generic equation of state P_k(rho) and the pseudopotential
+ *     psi = sqrt(rho/3 - P_k) (Sec. 2.3);
+ *   - the Kupershtokh single-neighbour force, eq. (kupershtokhforcing), applied
+ *     with the exact-difference method (Sec. 2.3);
+ *   - the axisymmetric force correction F_axis, eq. (multiphasecorrections), with
+ *     the isotropic stencils of eq. (fifthorderaccuratefinitedifference);
+ *   - the axisymmetric source h_i of eq. (axihz) (Sec. 2.2) and BGK collision,
+ *     eq. (lbm).
+ * All of that runs in HIP kernels for gfx950; the host side only validates
+ * arguments, lays out memory and launches.
+ *
+ * Grid: node (k, j) sits at z = k (k = 0..nz-1) and r = j + 1/2 (j = 0..nr-1).
+ * Host node fields are double arrays [nr][nz] (k fastest); a distribution is
+ * double [9][nr][nz] in the direction order
+ *   0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1)
+ * with components (c_z, c_r).
+ *
+ * Conventions for every entry point:
+ *   - returns LBM_OK (0) or a negative lbm_status; nothing throws across the ABI;
+ *   - host arrays are owned by the caller and only read or written during the call;
+ *   - device memory is owned by the library unless a workspace is adopted
+ *     (lbm_axi_batch_init_ws), in which case the caller keeps it alive until
+ *     lbm_axi_destroy and the library never frees it;
+ *   - a handle is bound to one HIP stream and is not thread-safe;
+ *   - lbm_axi_step is asynchronous; errors raised on the device (EOS domain,
+ *     non-finite values) are reported by the next synchronising call
+ *     (lbm_axi_sync, _moments, _mass, _laplace, _get_f).
+ */
+#ifndef LBM_AXI_H
+#define LBM_AXI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lbm_status;
+#define LBM_OK 0
+#define LBM_ERR_ARG (-1)         /* invalid argument or parameter set */
+#define LBM_ERR_ALLOC (-2)       /* device or host allocation failed, or workspace too small */
+#define LBM_ERR_HIP (-3)         /* a HIP runtime call failed */
+#define LBM_ERR_EOS_DOMAIN (-4)  /* rho <= 0 or rho/3 - P_k < 0 (psi not real) on some node */
+#define LBM_ERR_NONFINITE (-5)   /* a non-finite value appeared */
+#define LBM_ERR_UNSUPPORTED (-6) /* valid request this build does not implement */
+
+typedef enum { LBM_EOS_IDEAL = 0, LBM_EOS_VDW = 1, LBM_EOS_CS = 2 } lbm_eos_kind;
+typedef enum { LBM_TOP_FREE_SLIP = 0, LBM_TOP_NO_SLIP = 1 } lbm_top_bc;
+typedef enum { LBM_PREC_FP64 = 0, LBM_PREC_FP32 = 1 } lbm_precision;
+
+/* One simulation instance.  Sec. 2 of the paper defines every field except
+ * the Carnahan-Starling coefficients, which follow the usual form
+ *   P = lambda [rho R T (1 + e + e^2 - e^3)/(1 - e)^3 - a rho^2],  e = b rho / 4. */
+typedef struct {
+  int32_t nz, nr;            /* nz >= 1, nr >= 4 */
+  double tau;                /* BGK relaxation time > 1/2; nu = (tau - 1/2)/3 */
+  int32_t eos;               /* lbm_eos_kind */
+  double T;                  /* absolute EOS temperature (vdW: T/T_c since that EOS is reduced) */
+  double eos_a, eos_b, eos_R;/* Carnahan-Starling a, b, R (ignored otherwise) */
+  double lambda;             /* pressure scale of eq. (kupershtokvdwpressure); also scales CS */
+  double A;                  /* Kupershtokh mixing parameter, eq. (kupershtokhforcing) */
+  int32_t axisym;            /* 1: h_i and F_axis on (axisymmetric); 0: plain 2-D (z, r) plane */
+  int32_t faxis_sound;       /* 0: F_axis uses c_k^4 = (dP_k/drho)^2 (Sec. 2.3); 1: c_s^4 = 1/9 */
+  int32_t bc_top;            /* lbm_top_bc at r = nr */
+  double gz;                 /* uniform body-force density along z added to F */
+} lbm_axi_params;
+
+/* Launch shape of the fused step kernel (chosen by lbm_axi_autotune or set by hand). */
+typedef struct {
+  int32_t width;        /* lanes per workgroup along z: 64, 128, 256 or 512 (12 are halo) */
+  int32_t seg_rows;     /* rows of r per work item (>= 8), 0 = whole column */
+  int32_t persistent;   /* 1: persistent grid draining a work queue; 0: one workgroup per item */
+  int32_t grid;         /* persistent grid size, 0 = automatic */
+  int32_t xcd_swizzle;  /* 1: neighbouring work items go to the same XCD */
+} lbm_axi_launch;
+
+typedef struct lbm_axi_s* lbm_axi_t;
+
+/* Human-readable name of a status code (static storage). */
+const char* lbm_axi_status_string(lbm_status s);
+
+/* ---------------------------------------------------------------- host helpers */
+
+/* Critical point of the EOS in p (p->T ignored); vdW and CS only. */
+lbm_status lbm_axi_eos_critical(const lbm_axi_params* p, double* rho_c, double* T_c, double* P_c);
+
+/* Maxwell equal-area coexistence densities and saturation pressure at p->T < T_c. */
+lbm_status lbm_axi_eos_coexistence(const lbm_axi_params* p, double* rho_v, double* rho_l,
+                                   double* p_sat);
+
+/* ---------------------------------------------------------------- lifetime */
+
+/* Single instance: allocate device state and set f = E(rho0, u0) (eq. lbm's
+ * equilibrium, Sec. 2.1) as the populations after streaming at t = 0.
+ * rho0: host [nr][nz], required; uz0, ur0: host [nr][nz] or NULL for 0.
+ * precision: lbm_precision.  stream: hipStream_t, NULL = the library creates its own. */
+lbm_status lbm_axi_init(const lbm_axi_params* p, int32_t precision, const double* rho0,
+                        const double* uz0, const double* ur0, void* stream, lbm_axi_t* out);
+
+/* n independent instances (uneven sizes and parameters) advanced together by one
+ * launch per step.  params[k] and rho0[k] (host [nr_k][nz_k]) describe instance k. */
+lbm_status lbm_axi_batch_init(int32_t n, const lbm_axi_params* params, int32_t precision,
+                              const double* const* rho0, void* stream, lbm_axi_t* out);
+
+/* Device bytes needed for the two distribution buffers of an n-instance batch. */
+lbm_status lbm_axi_workspace_bytes(int32_t n, const lbm_axi_params* params, int32_t precision,
+                                   size_t* bytes);
+
+/* As lbm_axi_batch_init, but the distribution buffers live in a caller-owned
+ * device workspace of at least lbm_axi_workspace_bytes bytes (256-byte aligned). */
+lbm_status lbm_axi_batch_init_ws(int32_t n, const lbm_axi_params* params, int32_t precision,
+                                 const double* const* rho0, void* stream, void* workspace,
+                                 size_t workspace_bytes, lbm_axi_t* out);
+
+/* Release everything the library allocated; NULL is a no-op. */
+void lbm_axi_destroy(lbm_axi_t h);
+
+/* ---------------------------------------------------------------- time stepping */
+
+/* Enqueue nsteps >= 0 time steps of every instance on the handle's stream. */
+lbm_status lbm_axi_step(lbm_axi_t h, int64_t nsteps);
+
+/* As lbm_axi_step, then wait; *ms receives the HIP-event time of the launches
+ * on the handle's stream (kernel time, no host overhead between steps). */
+lbm_status lbm_axi_step_timed(lbm_axi_t h, int64_t nsteps, double* ms);
+
+/* Wait for the stream and report any device-side error. */
+lbm_status lbm_axi_sync(lbm_axi_t h);
+
+/* Per-instance device error bits (1: EOS domain left, 2: non-finite value; 0 = clean),
+ * flags is host int32 [n].  Synchronises; the bits stay set (the state is invalid). */
+lbm_status lbm_axi_errors(lbm_axi_t h, int32_t* flags);
+
+/* Replay steps as captured hipGraphs of `chunk` steps (even, >= 2); 0 = eager launches. */
+lbm_status lbm_axi_set_graph_chunk(lbm_axi_t h, int32_t chunk);
+
+/* ---------------------------------------------------------------- observables (synchronising) */
+
+/* rho and the physical velocity u = (j + F/2)/rho of instance k; host [nr][nz] outputs. */
+lbm_status lbm_axi_moments(lbm_axi_t h, int32_t k, double* rho, double* uz, double* ur);
+
+/* mass[k] = sum over nodes of 2 pi r_j rho, FP64, deterministic; mass is host [n]. */
+lbm_status lbm_axi_mass(lbm_axi_t h, double* mass);
+
+/* dp[k] = mean P_k(rho) over nodes closer than r_in[k] to (zc[k], 0) minus the mean
+ * over nodes farther than r_out[k] (Young-Laplace, eq. laplacepressure); host [n] arrays. */
+lbm_status lbm_axi_laplace(lbm_axi_t h, const double* zc, const double* r_in,
+                           const double* r_out, double* dp);
+
+/* Checkpoint: the post-streaming populations of instance k as host double [9][nr][nz]. */
+lbm_status lbm_axi_get_f(lbm_axi_t h, int32_t k, double* f);
+
+/* Resume: replace the state of instance k by host double [9][nr][nz] post-streaming populations. */
+lbm_status lbm_axi_set_f(lbm_axi_t h, int32_t k, const double* f);
+
+/* ---------------------------------------------------------------- launch shape and tuning */
+
+lbm_status lbm_axi_get_launch(lbm_axi_t h, lbm_axi_launch* cfg);
+lbm_status lbm_axi_set_launch(lbm_axi_t h, const lbm_axi_launch* cfg);
+
+/* Time every candidate launch shape for steps_per_trial steps (state saved and
+ * restored on the device), keep the fastest, return it and its ms per step. */
+lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch* best,
+                            double* best_ms_per_step);
+
+/* Sizes: number of instances, total nodes, and bytes of one distribution buffer. */
+lbm_status lbm_axi_sizes(lbm_axi_t h, int32_t* n, int64_t* nodes, int64_t* f_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,781 @@
+// Host side of the C ABI in lbm_axi.h: argument checks, device memory layout,
+// work lists, launches, hipGraph chunks and the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lbm_axi.h"
+#include "lbm_axi_internal.h"
+
+using namespace lbm;
+
+struct lbm_axi_s {
+  int n = 0;
+  int prec = LBM_PREC_FP64;
+  std::vector<lbm_axi_params> prm;
+  std::vector<InstDev> hinst;
+  std::vector<long long> base;
+  long long plane = 0;  // elements per direction plane (all instances, padded)
+  long long nodes = 0;  // real nodes
+  size_t esize = 8;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  void* fbuf[2] = {nullptr, nullptr};
+  bool own_f = false;
+  int cur = 0;  // fbuf[cur] holds the post-collision planes of the last step
+  InstDev* d_inst = nullptr;
+  WorkItem* d_items = nullptr;
+  int n_items = 0;
+  size_t items_cap = 0;
+  int* d_queue = nullptr;
+  int* d_err = nullptr;
+  RowRef* d_rows = nullptr;
+  int* d_row_start = nullptr;
+  int n_rows = 0;
+  double* d_part = nullptr;
+  double* d_out = nullptr;
+  double* d_geo = nullptr;
+  lbm_axi_launch launch{};
+  int cus = 256;
+  int graph_chunk = 0;
+  hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+#define HIPCHK(call)                             \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return LBM_ERR_HIP;    \
+  } while (0)
+
+lbm_status check_params(const lbm_axi_params& p) {
+  if (p.nz < 1 || p.nr < 4) return LBM_ERR_ARG;
+  if ((long long)p.nz * p.nr > (1LL << 31)) return LBM_ERR_ARG;
+  if (!(p.tau > 0.5) || !std::isfinite(p.tau)) return LBM_ERR_ARG;
+  if (p.eos < LBM_EOS_IDEAL || p.eos > LBM_EOS_CS) return LBM_ERR_ARG;
+  if (p.eos == LBM_EOS_CS && !(p.eos_b > 0.0)) return LBM_ERR_ARG;
+  if (p.eos != LBM_EOS_IDEAL && !(p.lambda > 0.0)) return LBM_ERR_ARG;
+  if (p.bc_top != LBM_TOP_FREE_SLIP && p.bc_top != LBM_TOP_NO_SLIP) return LBM_ERR_ARG;
+  if (p.axisym != 0 && p.axisym != 1) return LBM_ERR_ARG;
+  if (p.faxis_sound != 0 && p.faxis_sound != 1) return LBM_ERR_ARG;
+  if (!std::isfinite(p.A) || !std::isfinite(p.gz) || !std::isfinite(p.T)) return LBM_ERR_ARG;
+  return LBM_OK;
+}
+
+// Host check that an initial density field lies in the EOS domain (psi real), so that a
+// bad input is refused before anything is launched.
+lbm_status check_rho0(const lbm_axi_params& p, const double* rho) {
+  const long long n = (long long)p.nz * p.nr;
+  for (long long x = 0; x < n; ++x) {
+    const double r = rho[x];
+    if (!std::isfinite(r)) return LBM_ERR_NONFINITE;
+    if (!(r > 0.0)) return LBM_ERR_EOS_DOMAIN;
+    if (p.eos == LBM_EOS_IDEAL) continue;
+    double P;
+    if (p.eos == LBM_EOS_VDW) {
+      if (!(r < 3.0)) return LBM_ERR_EOS_DOMAIN;
+      P = p.lambda * (8.0 * r * p.T / (3.0 - r) - 3.0 * r * r);
+    } else {
+      const double e = 0.25 * p.eos_b * r;
+      if (!(e < 1.0)) return LBM_ERR_EOS_DOMAIN;
+      const double m = 1.0 - e;
+      P = p.lambda * (p.eos_R * p.T * r * (1.0 + e * (1.0 + e * (1.0 - e))) / (m * m * m) - p.eos_a * r * r);
+    }
+    if (!(r / 3.0 - P >= 0.0)) return LBM_ERR_EOS_DOMAIN;
+  }
+  return LBM_OK;
+}
+
+// Storage reference density of an FP32 instance: the median of (a sample of) its initial
+// density, i.e. the density of the phase that fills most of the domain.
+double reference_density(const lbm_axi_params& p, const double* rho0) {
+  const long long n = (long long)p.nz * p.nr;
+  const long long stride = std::max(1LL, n / 1000003);
+  std::vector<double> s;
+  for (long long x = 0; x < n; x += stride) s.push_back(rho0[x]);
+  std::nth_element(s.begin(), s.begin() + s.size() / 2, s.end());
+  return s[s.size() / 2];
+}
+
+InstDev make_inst(const lbm_axi_params& p, long long base, double rho_ref) {
+  InstDev d{};
+  d.rho_ref = rho_ref;
+  d.psi_ref = rho_ref > 0.0 ? eos_psi(p, rho_ref) : 0.0;
+  d.base = base;
+  d.nz = p.nz;
+  d.nr = p.nr;
+  d.eos = p.eos;
+  d.axisym = p.axisym;
+  d.faxis_sound = p.faxis_sound;
+  d.bc_top = p.bc_top;
+  d.T = p.T;
+  d.a = p.eos_a;
+  d.b = p.eos_b;
+  d.R = p.eos_R;
+  d.lam = p.lambda;
+  d.A = p.A;
+  d.omega = 1.0 / p.tau;
+  d.nu = (p.tau - 0.5) / 3.0;
+  d.gz = p.gz;
+  return d;
+}
+
+bool valid_width(int w) { return w == 64 || w == 128 || w == 256; }
+
+lbm_axi_launch default_launch(const lbm_axi_s* h) {
+  lbm_axi_launch c{};
+  int maxnz = 0;
+  for (auto& p : h->prm) maxnz = std::max(maxnz, p.nz);
+  c.width = maxnz >= 244 ? 256 : (maxnz >= 116 ? 128 : 64);
+  c.seg_rows = 256;
+  c.persistent = h->n > 1 ? 1 : 0;
+  c.grid = 0;
+  c.xcd_swizzle = 1;
+  return c;
+}
+
+// Strips of width - 12 output columns times row segments, for every instance.
+std::vector<WorkItem> build_items(const lbm_axi_s* h, const lbm_axi_launch& c, int only_inst) {
+  std::vector<WorkItem> items;
+  const int wout = c.width - 12;
+  for (int k = 0; k < h->n; ++k) {
+    if (only_inst >= 0 && k != only_inst) continue;
+    const auto& p = h->prm[k];
+    const int seg = c.seg_rows > 0 ? c.seg_rows : p.nr;
+    const int nstrip = std::max(1, (p.nz + wout - 1) / wout);
+    for (int s = 0; s < p.nr; s += seg)
+      for (int q = 0; q < nstrip; ++q) {
+        WorkItem w;
+        w.inst = k;
+        w.k0 = q * wout;
+        w.ncols = std::min(wout, p.nz - w.k0);
+        w.s = s;
+        w.e = std::min(p.nr, s + seg);
+        items.push_back(w);
+      }
+  }
+  if (c.persistent) {
+    // longest first (rows swept, halo included), so the queue drains evenly
+    auto cost = [](const WorkItem& w) { return (w.e - w.s) + std::min(6, w.s) + 6; };
+    std::stable_sort(items.begin(), items.end(),
+                     [&](const WorkItem& a, const WorkItem& b) { return cost(a) > cost(b); });
+  }
+  return items;
+}
+
+lbm_status upload_items(lbm_axi_s* h, const std::vector<WorkItem>& items) {
+  if (items.size() > h->items_cap) {
+    if (h->d_items) HIPCHK(hipFree(h->d_items));
+    h->d_items = nullptr;
+    const size_t cap = std::max<size_t>(items.size(), 1024);
+    HIPCHK(hipMalloc(&h->d_items, cap * sizeof(WorkItem)));
+    h->items_cap = cap;
+  }
+  HIPCHK(hipMemcpyAsync(h->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
+                        h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->n_items = (int)items.size();
+  return LBM_OK;
+}
+
+void drop_graph(lbm_axi_s* h) {
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+}
+
+lbm_status apply_launch(lbm_axi_s* h, const lbm_axi_launch& c) {
+  if (!valid_width(c.width)) return LBM_ERR_UNSUPPORTED;
+  if (c.seg_rows != 0 && c.seg_rows < 8) return LBM_ERR_ARG;
+  if (c.grid < 0) return LBM_ERR_ARG;
+  lbm_status s = upload_items(h, build_items(h, c, -1));
+  if (s != LBM_OK) return s;
+  h->launch = c;
+  drop_graph(h);
+  return LBM_OK;
+}
+
+int grid_of(const lbm_axi_s* h) {
+  if (!h->launch.persistent) return h->n_items;
+  int g = h->launch.grid > 0 ? h->launch.grid : h->cus * (h->launch.width <= 128 ? 8 : 4);
+  return std::max(1, std::min(g, h->n_items));
+}
+
+template <typename R>
+hipError_t enqueue_sweep(lbm_axi_s* h, bool moments, int inst_for_moments, double* mr, double* mz,
+                         double* mu) {
+  SweepArgs<R> g{};
+  g.fin = static_cast<const R*>(h->fbuf[h->cur]);
+  g.fout = static_cast<R*>(h->fbuf[h->cur ^ 1]);
+  g.plane = h->plane;
+  g.inst = h->d_inst;
+  g.items = h->d_items;
+  g.n_items = h->n_items;
+  g.xcd_swizzle = h->launch.xcd_swizzle;
+  g.queue = h->d_queue;
+  g.err = h->d_err;
+  g.mrho = mr;
+  g.muz = mz;
+  g.mur = mu;
+  (void)inst_for_moments;
+  return sweep_dispatch<R>(g, h->launch.width, moments, moments ? false : h->launch.persistent != 0,
+                           moments ? h->n_items : grid_of(h), h->stream);
+}
+
+lbm_status enqueue_steps_eager(lbm_axi_s* h, int64_t nsteps) {
+  for (int64_t s = 0; s < nsteps; ++s) {
+    hipError_t e = h->prec == LBM_PREC_FP32 ? enqueue_sweep<float>(h, false, -1, nullptr, nullptr, nullptr)
+                                            : enqueue_sweep<double>(h, false, -1, nullptr, nullptr, nullptr);
+    if (e != hipSuccess) return LBM_ERR_HIP;
+    h->cur ^= 1;
+  }
+  return LBM_OK;
+}
+
+lbm_status capture_graph(lbm_axi_s* h) {
+  drop_graph(h);
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  const int cur0 = h->cur;
+  lbm_status s = enqueue_steps_eager(h, h->graph_chunk);
+  hipError_t ee = hipStreamEndCapture(h->stream, &graph);
+  h->cur = cur0;  // capture does not run anything; an even chunk returns to the same buffer
+  if (s != LBM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (ee != hipSuccess) return LBM_ERR_HIP;
+  hipError_t ie = hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) {
+    h->gexec = nullptr;
+    return LBM_ERR_HIP;
+  }
+  return LBM_OK;
+}
+
+lbm_status enqueue_steps(lbm_axi_s* h, int64_t nsteps) {
+  if (h->graph_chunk > 0 && nsteps >= h->graph_chunk) {
+    if (!h->gexec) {
+      lbm_status s = capture_graph(h);
+      if (s != LBM_OK) return s;
+    }
+    while (nsteps >= h->graph_chunk) {
+      HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+      nsteps -= h->graph_chunk;
+    }
+  }
+  return enqueue_steps_eager(h, nsteps);
+}
+
+lbm_status read_err(lbm_axi_s* h) {
+  int e = 0;
+  HIPCHK(hipMemcpyAsync(&e, h->d_err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (e & 2) return LBM_ERR_NONFINITE;
+  if (e & 1) return LBM_ERR_EOS_DOMAIN;
+  return LBM_OK;
+}
+
+size_t f_bytes_of(int n, const lbm_axi_params* params, int prec, long long* plane_out,
+                  std::vector<long long>* bases) {
+  long long off = 0;
+  for (int k = 0; k < n; ++k) {
+    if (bases) bases->push_back(off);
+    const long long nn = (long long)params[k].nz * params[k].nr;
+    off += (nn + 63) / 64 * 64;  // every instance starts on a 256-byte boundary
+  }
+  if (plane_out) *plane_out = off;
+  return (size_t)off * 9 * (prec == LBM_PREC_FP32 ? 4 : 8);
+}
+
+void free_all(lbm_axi_s* h) {
+  drop_graph(h);
+  if (h->own_f) {
+    if (h->fbuf[0]) (void)hipFree(h->fbuf[0]);
+  }
+  void* ptrs[] = {h->d_inst, h->d_items, h->d_queue, h->d_err, h->d_rows, h->d_row_start,
+                  h->d_part, h->d_out, h->d_geo};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+}
+
+template <typename R>
+hipError_t unstream_into(lbm_axi_s* h, int k, const double* rho0, const double* uz0, const double* ur0,
+                         const double* f0) {
+  const auto& p = h->prm[k];
+  R* dst = static_cast<R*>(h->fbuf[h->cur]) + h->base[k];
+  return launch_unstream<R>(dst, h->plane, p.nz, p.nr, p.bc_top, h->hinst[k].rho_ref, rho0, uz0, ur0, f0,
+                            h->stream);
+}
+
+// Upload host fields of instance k into a temporary device buffer and build its planes.
+lbm_status load_instance(lbm_axi_s* h, int k, const double* rho0, const double* uz0, const double* ur0,
+                         const double* f0) {
+  const auto& p = h->prm[k];
+  const size_t n = (size_t)p.nz * p.nr;
+  const size_t count = f0 ? 9 * n : 3 * n;
+  double* tmp = nullptr;
+  HIPCHK(hipMalloc(&tmp, count * sizeof(double)));
+  lbm_status st = LBM_OK;
+  do {
+    double *d_rho = nullptr, *d_uz = nullptr, *d_ur = nullptr, *d_f = nullptr;
+    if (f0) {
+      d_f = tmp;
+      if (hipMemcpyAsync(d_f, f0, 9 * n * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+        st = LBM_ERR_HIP;
+        break;
+      }
+    } else {
+      d_rho = tmp;
+      if (hipMemcpyAsync(d_rho, rho0, n * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+        st = LBM_ERR_HIP;
+        break;
+      }
+      if (uz0) {
+        d_uz = tmp + n;
+        if (hipMemcpyAsync(d_uz, uz0, n * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+          st = LBM_ERR_HIP;
+          break;
+        }
+      }
+      if (ur0) {
+        d_ur = tmp + 2 * n;
+        if (hipMemcpyAsync(d_ur, ur0, n * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+          st = LBM_ERR_HIP;
+          break;
+        }
+      }
+    }
+    hipError_t e = h->prec == LBM_PREC_FP32 ? unstream_into<float>(h, k, d_rho, d_uz, d_ur, d_f)
+                                            : unstream_into<double>(h, k, d_rho, d_uz, d_ur, d_f);
+    if (e != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) st = LBM_ERR_HIP;
+  } while (0);
+  (void)hipFree(tmp);
+  return st;
+}
+
+lbm_status create(int n, const lbm_axi_params* params, int prec, const double* const* rho0, void* stream,
+                  void* workspace, size_t ws_bytes, lbm_axi_t* out) {
+  if (!out || n < 1 || !params) return LBM_ERR_ARG;
+  *out = nullptr;
+  if (prec != LBM_PREC_FP64 && prec != LBM_PREC_FP32) return LBM_ERR_ARG;
+  for (int k = 0; k < n; ++k) {
+    lbm_status s = check_params(params[k]);
+    if (s != LBM_OK) return s;
+  }
+  lbm_axi_s* h = new (std::nothrow) lbm_axi_s();
+  if (!h) return LBM_ERR_ALLOC;
+  h->n = n;
+  h->prec = prec;
+  h->esize = prec == LBM_PREC_FP32 ? 4 : 8;
+  h->prm.assign(params, params + n);
+  const size_t fb = f_bytes_of(n, params, prec, &h->plane, &h->base);
+  for (int k = 0; k < n; ++k) {
+    const double rref = prec == LBM_PREC_FP32 ? reference_density(params[k], rho0[k]) : 0.0;
+    h->hinst.push_back(make_inst(params[k], h->base[k], rref));
+    h->nodes += (long long)params[k].nz * params[k].nr;
+  }
+  lbm_status st = LBM_OK;
+  auto fail = [&](lbm_status s) {
+    free_all(h);
+    delete h;
+    return s;
+  };
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(LBM_ERR_HIP);
+  h->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  if (stream) {
+    h->stream = static_cast<hipStream_t>(stream);
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) return fail(LBM_ERR_HIP);
+    h->own_stream = true;
+  }
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
+    return fail(LBM_ERR_HIP);
+  if (workspace) {
+    if (ws_bytes < 2 * fb || (reinterpret_cast<uintptr_t>(workspace) & 255)) return fail(LBM_ERR_ALLOC);
+    h->fbuf[0] = workspace;
+    h->own_f = false;
+  } else {
+    if (hipMalloc(&h->fbuf[0], 2 * fb) != hipSuccess) return fail(LBM_ERR_ALLOC);
+    h->own_f = true;
+  }
+  h->fbuf[1] = static_cast<char*>(h->fbuf[0]) + fb;
+  // rows of every instance, for the reductions
+  std::vector<RowRef> rows;
+  std::vector<int> row_start;
+  for (int k = 0; k < n; ++k) {
+    row_start.push_back((int)rows.size());
+    for (int j = 0; j < params[k].nr; ++j) rows.push_back(RowRef{k, j});
+  }
+  row_start.push_back((int)rows.size());
+  h->n_rows = (int)rows.size();
+  if (hipMalloc(&h->d_inst, n * sizeof(InstDev)) != hipSuccess ||
+      hipMalloc(&h->d_queue, 2 * sizeof(int)) != hipSuccess || hipMalloc(&h->d_err, (n + 1) * sizeof(int)) != hipSuccess ||
+      hipMalloc(&h->d_rows, rows.size() * sizeof(RowRef)) != hipSuccess ||
+      hipMalloc(&h->d_row_start, row_start.size() * sizeof(int)) != hipSuccess ||
+      hipMalloc(&h->d_part, rows.size() * 4 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&h->d_out, n * sizeof(double)) != hipSuccess ||
+      hipMalloc(&h->d_geo, 3 * n * sizeof(double)) != hipSuccess)
+    return fail(LBM_ERR_ALLOC);
+  if (hipMemcpy(h->d_inst, h->hinst.data(), n * sizeof(InstDev), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->d_rows, rows.data(), rows.size() * sizeof(RowRef), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->d_row_start, row_start.data(), row_start.size() * sizeof(int), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemset(h->d_queue, 0, 2 * sizeof(int)) != hipSuccess || hipMemset(h->d_err, 0, (n + 1) * sizeof(int)) != hipSuccess)
+    return fail(LBM_ERR_HIP);
+  st = apply_launch(h, default_launch(h));
+  if (st != LBM_OK) return fail(st);
+  *out = h;
+  return LBM_OK;
+}
+
+template <typename R>
+hipError_t enqueue_moments(lbm_axi_s* h, int k, double* mr, double* mz, double* mu) {
+  // A dedicated work list for instance k, non-persistent, same width.
+  SweepArgs<R> g{};
+  g.fin = static_cast<const R*>(h->fbuf[h->cur]);
+  g.fout = static_cast<R*>(h->fbuf[h->cur ^ 1]);
+  g.plane = h->plane;
+  g.inst = h->d_inst;
+  g.items = h->d_items;
+  g.n_items = h->n_items;
+  g.xcd_swizzle = 0;
+  g.queue = h->d_queue;
+  g.err = h->d_err;
+  g.mrho = mr;
+  g.muz = mz;
+  g.mur = mu;
+  (void)k;
+  return sweep_dispatch<R>(g, h->launch.width, true, false, h->n_items, h->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_axi_status_string(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_ERR_ARG: return "invalid argument";
+    case LBM_ERR_ALLOC: return "allocation failed or workspace too small";
+    case LBM_ERR_HIP: return "HIP runtime error";
+    case LBM_ERR_EOS_DOMAIN: return "equation-of-state domain left (rho <= 0 or psi not real)";
+    case LBM_ERR_NONFINITE: return "non-finite value";
+    case LBM_ERR_UNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+  }
+}
+
+lbm_status lbm_axi_eos_critical(const lbm_axi_params* p, double* rho_c, double* T_c, double* P_c) {
+  if (!p || !rho_c || !T_c || !P_c) return LBM_ERR_ARG;
+  return eos_critical(*p, rho_c, T_c, P_c);
+}
+
+lbm_status lbm_axi_eos_coexistence(const lbm_axi_params* p, double* rho_v, double* rho_l, double* p_sat) {
+  if (!p || !rho_v || !rho_l || !p_sat) return LBM_ERR_ARG;
+  return eos_coexistence(*p, rho_v, rho_l, p_sat);
+}
+
+lbm_status lbm_axi_workspace_bytes(int32_t n, const lbm_axi_params* params, int32_t precision, size_t* bytes) {
+  if (n < 1 || !params || !bytes) return LBM_ERR_ARG;
+  if (precision != LBM_PREC_FP64 && precision != LBM_PREC_FP32) return LBM_ERR_ARG;
+  *bytes = 2 * f_bytes_of(n, params, precision, nullptr, nullptr);
+  return LBM_OK;
+}
+
+lbm_status lbm_axi_batch_init_ws(int32_t n, const lbm_axi_params* params, int32_t precision,
+                                 const double* const* rho0, void* stream, void* workspace,
+                                 size_t workspace_bytes, lbm_axi_t* out) {
+  if (!rho0 || !params || n < 1 || !out) return LBM_ERR_ARG;
+  for (int k = 0; k < n; ++k) {
+    if (!rho0[k]) return LBM_ERR_ARG;
+    lbm_status s = check_params(params[k]);
+    if (s != LBM_OK) return s;
+    s = check_rho0(params[k], rho0[k]);
+    if (s != LBM_OK) return s;
+  }
+  lbm_axi_t h = nullptr;
+  lbm_status s = create(n, params, precision, rho0, stream, workspace, workspace_bytes, &h);
+  if (s != LBM_OK) return s;
+  for (int k = 0; k < n && s == LBM_OK; ++k) s = load_instance(h, k, rho0[k], nullptr, nullptr, nullptr);
+  if (s != LBM_OK) {
+    free_all(h);
+    delete h;
+    return s;
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+lbm_status lbm_axi_batch_init(int32_t n, const lbm_axi_params* params, int32_t precision,
+                              const double* const* rho0, void* stream, lbm_axi_t* out) {
+  return lbm_axi_batch_init_ws(n, params, precision, rho0, stream, nullptr, 0, out);
+}
+
+lbm_status lbm_axi_init(const lbm_axi_params* p, int32_t precision, const double* rho0, const double* uz0,
+                        const double* ur0, void* stream, lbm_axi_t* out) {
+  if (!p || !rho0 || !out) return LBM_ERR_ARG;
+  lbm_status s = check_params(*p);
+  if (s != LBM_OK) return s;
+  s = check_rho0(*p, rho0);
+  if (s != LBM_OK) return s;
+  const long long n = (long long)p->nz * p->nr;
+  for (const double* u : {uz0, ur0})
+    if (u)
+      for (long long x = 0; x < n; ++x)
+        if (!std::isfinite(u[x])) return LBM_ERR_NONFINITE;
+  lbm_axi_t h = nullptr;
+  s = create(1, p, precision, &rho0, stream, nullptr, 0, &h);
+  if (s != LBM_OK) return s;
+  s = load_instance(h, 0, rho0, uz0, ur0, nullptr);
+  if (s != LBM_OK) {
+    free_all(h);
+    delete h;
+    return s;
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+void lbm_axi_destroy(lbm_axi_t h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  free_all(h);
+  delete h;
+}
+
+lbm_status lbm_axi_step(lbm_axi_t h, int64_t nsteps) {
+  if (!h || nsteps < 0) return LBM_ERR_ARG;
+  return enqueue_steps(h, nsteps);
+}
+
+lbm_status lbm_axi_step_timed(lbm_axi_t h, int64_t nsteps, double* ms) {
+  if (!h || nsteps < 0 || !ms) return LBM_ERR_ARG;
+  HIPCHK(hipEventRecord(h->ev0, h->stream));
+  lbm_status s = enqueue_steps(h, nsteps);
+  if (s != LBM_OK) return s;
+  HIPCHK(hipEventRecord(h->ev1, h->stream));
+  HIPCHK(hipEventSynchronize(h->ev1));
+  float t = 0.f;
+  HIPCHK(hipEventElapsedTime(&t, h->ev0, h->ev1));
+  *ms = t;
+  return read_err(h);
+}
+
+lbm_status lbm_axi_sync(lbm_axi_t h) {
+  if (!h) return LBM_ERR_ARG;
+  return read_err(h);
+}
+
+lbm_status lbm_axi_errors(lbm_axi_t h, int32_t* flags) {
+  if (!h || !flags) return LBM_ERR_ARG;
+  HIPCHK(hipMemcpyAsync(flags, h->d_err + 1, h->n * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_axi_set_graph_chunk(lbm_axi_t h, int32_t chunk) {
+  if (!h || chunk < 0 || (chunk > 0 && (chunk < 2 || (chunk & 1)))) return LBM_ERR_ARG;
+  drop_graph(h);
+  h->graph_chunk = chunk;
+  return LBM_OK;
+}
+
+lbm_status lbm_axi_moments(lbm_axi_t h, int32_t k, double* rho, double* uz, double* ur) {
+  if (!h || k < 0 || k >= h->n || !rho || !uz || !ur) return LBM_ERR_ARG;
+  const auto& p = h->prm[k];
+  const size_t n = (size_t)p.nz * p.nr;
+  double* tmp = nullptr;
+  HIPCHK(hipMalloc(&tmp, 3 * n * sizeof(double)));
+  // moments of instance k: a work list restricted to it
+  const int saved_items = h->n_items;
+  std::vector<WorkItem> items = build_items(h, lbm_axi_launch{h->launch.width, h->launch.seg_rows, 0, 0, 0}, k);
+  WorkItem* d_items = nullptr;
+  lbm_status st = LBM_OK;
+  if (hipMalloc(&d_items, items.size() * sizeof(WorkItem)) != hipSuccess) st = LBM_ERR_ALLOC;
+  if (st == LBM_OK &&
+      hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, h->stream) !=
+          hipSuccess)
+    st = LBM_ERR_HIP;
+  if (st == LBM_OK) {
+    WorkItem* keep = h->d_items;
+    h->d_items = d_items;
+    h->n_items = (int)items.size();
+    hipError_t e = h->prec == LBM_PREC_FP32 ? enqueue_moments<float>(h, k, tmp, tmp + n, tmp + 2 * n)
+                                            : enqueue_moments<double>(h, k, tmp, tmp + n, tmp + 2 * n);
+    h->d_items = keep;
+    h->n_items = saved_items;
+    if (e != hipSuccess) st = LBM_ERR_HIP;
+  }
+  if (st == LBM_OK) {
+    if (hipMemcpyAsync(rho, tmp, n * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipMemcpyAsync(uz, tmp + n, n * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipMemcpyAsync(ur, tmp + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      st = LBM_ERR_HIP;
+  }
+  (void)hipFree(d_items);
+  (void)hipFree(tmp);
+  if (st != LBM_OK) return st;
+  return read_err(h);
+}
+
+static lbm_status reduce(lbm_axi_t h, int K, double* out) {
+  hipError_t e = h->prec == LBM_PREC_FP32
+                     ? launch_rows<float>(K, static_cast<const float*>(h->fbuf[h->cur]), h->plane, h->d_inst,
+                                          h->d_rows, h->n_rows, h->d_geo, h->d_part, h->stream)
+                     : launch_rows<double>(K, static_cast<const double*>(h->fbuf[h->cur]), h->plane, h->d_inst,
+                                           h->d_rows, h->n_rows, h->d_geo, h->d_part, h->stream);
+  if (e != hipSuccess) return LBM_ERR_HIP;
+  HIPCHK(launch_finish(K, h->d_part, h->d_row_start, h->d_inst, h->n, h->d_out, h->stream));
+  HIPCHK(hipMemcpyAsync(out, h->d_out, h->n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return read_err(h);
+}
+
+lbm_status lbm_axi_mass(lbm_axi_t h, double* mass) {
+  if (!h || !mass) return LBM_ERR_ARG;
+  return reduce(h, 1, mass);
+}
+
+lbm_status lbm_axi_laplace(lbm_axi_t h, const double* zc, const double* r_in, const double* r_out, double* dp) {
+  if (!h || !zc || !r_in || !r_out || !dp) return LBM_ERR_ARG;
+  std::vector<double> geo(3 * h->n);
+  for (int k = 0; k < h->n; ++k) {
+    geo[3 * k] = zc[k];
+    geo[3 * k + 1] = r_in[k];
+    geo[3 * k + 2] = r_out[k];
+  }
+  HIPCHK(hipMemcpyAsync(h->d_geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  return reduce(h, 4, dp);
+}
+
+lbm_status lbm_axi_get_f(lbm_axi_t h, int32_t k, double* f) {
+  if (!h || k < 0 || k >= h->n || !f) return LBM_ERR_ARG;
+  const auto& p = h->prm[k];
+  const size_t n = (size_t)p.nz * p.nr;
+  double* tmp = nullptr;
+  HIPCHK(hipMalloc(&tmp, 9 * n * sizeof(double)));
+  hipError_t e =
+      h->prec == LBM_PREC_FP32
+          ? launch_export<float>(static_cast<const float*>(h->fbuf[h->cur]) + h->base[k], h->plane, p.nz, p.nr,
+                                 p.bc_top, h->hinst[k].rho_ref, tmp, h->stream)
+          : launch_export<double>(static_cast<const double*>(h->fbuf[h->cur]) + h->base[k], h->plane, p.nz,
+                                  p.nr, p.bc_top, h->hinst[k].rho_ref, tmp, h->stream);
+  lbm_status st = LBM_OK;
+  if (e != hipSuccess ||
+      hipMemcpyAsync(f, tmp, 9 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    st = LBM_ERR_HIP;
+  (void)hipFree(tmp);
+  if (st != LBM_OK) return st;
+  return read_err(h);
+}
+
+lbm_status lbm_axi_set_f(lbm_axi_t h, int32_t k, const double* f) {
+  if (!h || k < 0 || k >= h->n || !f) return LBM_ERR_ARG;
+  const auto& p = h->prm[k];
+  const size_t n = (size_t)p.nz * p.nr;
+  for (size_t x = 0; x < 9 * n; ++x)
+    if (!std::isfinite(f[x])) return LBM_ERR_NONFINITE;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return load_instance(h, k, nullptr, nullptr, nullptr, f);
+}
+
+lbm_status lbm_axi_get_launch(lbm_axi_t h, lbm_axi_launch* cfg) {
+  if (!h || !cfg) return LBM_ERR_ARG;
+  *cfg = h->launch;
+  return LBM_OK;
+}
+
+lbm_status lbm_axi_set_launch(lbm_axi_t h, const lbm_axi_launch* cfg) {
+  if (!h || !cfg) return LBM_ERR_ARG;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return apply_launch(h, *cfg);
+}
+
+lbm_status lbm_axi_sizes(lbm_axi_t h, int32_t* n, int64_t* nodes, int64_t* f_bytes) {
+  if (!h) return LBM_ERR_ARG;
+  if (n) *n = h->n;
+  if (nodes) *nodes = h->nodes;
+  if (f_bytes) *f_bytes = (int64_t)(h->plane * 9 * (long long)h->esize);
+  return LBM_OK;
+}
+
+lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch* best, double* best_ms) {
+  if (!h || steps_per_trial < 1) return LBM_ERR_ARG;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const size_t fb = (size_t)h->plane * 9 * h->esize;
+  void* save = nullptr;
+  HIPCHK(hipMalloc(&save, fb));
+  const int cur0 = h->cur;
+  lbm_status st = LBM_OK;
+  if (hipMemcpyAsync(save, h->fbuf[cur0], fb, hipMemcpyDeviceToDevice, h->stream) != hipSuccess) st = LBM_ERR_HIP;
+  const lbm_axi_launch keep = h->launch;
+  const int keep_chunk = h->graph_chunk;
+  h->graph_chunk = 0;
+  lbm_axi_launch win = keep;
+  double win_ms = 1e300;
+  int maxnz = 0;
+  for (auto& p : h->prm) maxnz = std::max(maxnz, p.nz);
+  const int widths[] = {64, 128, 256};
+  const int segs[] = {64, 128, 256, 512, 0};
+  for (int w : widths) {
+    if (st != LBM_OK) break;
+    if (w > 64 && maxnz + 12 <= w / 2) continue;  // most lanes would duplicate columns
+    for (int sg : segs)
+      for (int pers = 0; pers <= 1 && st == LBM_OK; ++pers) {
+        lbm_axi_launch c{w, sg, pers, 0, 1};
+        if (apply_launch(h, c) != LBM_OK) continue;
+        if (enqueue_steps_eager(h, 1) != LBM_OK) {  // warm-up
+          st = LBM_ERR_HIP;
+          break;
+        }
+        double ms = 0.0;
+        if (hipEventRecord(h->ev0, h->stream) != hipSuccess || enqueue_steps_eager(h, steps_per_trial) != LBM_OK ||
+            hipEventRecord(h->ev1, h->stream) != hipSuccess || hipEventSynchronize(h->ev1) != hipSuccess) {
+          st = LBM_ERR_HIP;
+          break;
+        }
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, h->ev0, h->ev1);
+        ms = t / steps_per_trial;
+        if (ms < win_ms) {
+          win_ms = ms;
+          win = c;
+        }
+        // back to the saved state
+        h->cur = cur0;
+        if (hipMemcpyAsync(h->fbuf[cur0], save, fb, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
+          st = LBM_ERR_HIP;
+      }
+  }
+  (void)hipStreamSynchronize(h->stream);
+  (void)hipFree(save);
+  h->graph_chunk = keep_chunk;
+  lbm_status s2 = apply_launch(h, st == LBM_OK ? win : keep);
+  if (st != LBM_OK) return st;
+  if (s2 != LBM_OK) return s2;
+  if (best) *best = win;
+  if (best_ms) *best_ms = win_ms;
+  // a failed candidate could have raised the device error word: clear it with the state restored
+  HIPCHK(hipMemsetAsync(h->d_err, 0, (h->n + 1) * sizeof(int), h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+}  // extern "C"

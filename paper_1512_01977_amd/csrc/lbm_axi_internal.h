@@ -1,0 +1,73 @@
+// Internal declarations shared by the library's translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lbm_axi.h"
+
+namespace lbm {
+
+lbm_status eos_critical(const lbm_axi_params& p, double* rho_c, double* T_c, double* P_c);
+lbm_status eos_coexistence(const lbm_axi_params& p, double* rho_v, double* rho_l, double* p_sat);
+double eos_psi(const lbm_axi_params& p, double rho);  // sqrt(rho/3 - P_k), 0 for the ideal gas
+
+// Per-instance constants as the kernels read them (uniform, loaded through the scalar cache).
+struct InstDev {
+  long long base;    // index of node (0, 0) of the instance inside every distribution plane
+  int nz, nr;
+  int eos, axisym, faxis_sound, bc_top;
+  double T, a, b, R, lam;  // EOS coefficients (FP64 in every precision)
+  double A, omega, nu, gz; // A, 1/tau, (tau - 1/2)/3, body force density
+  // Storage shift: the planes hold g_i = f_i - w_i rho_ref and the psi ring holds
+  // psi - psi_ref, psi_ref = psi(rho_ref).  In FP32 this keeps the momentum (a small
+  // difference of O(rho) populations) and the psi gradients at full relative precision;
+  // FP64 uses rho_ref = psi_ref = 0.
+  double rho_ref, psi_ref;
+};
+
+// One unit of work of the fused step kernel: a strip of output columns
+// [k0, k0 + ncols) of instance `inst`, rows [s, e).
+struct WorkItem {
+  int inst, k0, ncols, s, e;
+};
+
+// Arguments of the fused step kernel.
+template <typename R>
+struct SweepArgs {
+  const R* __restrict__ fin;   // post-collision planes of the previous step
+  R* __restrict__ fout;        // post-collision planes of this step
+  long long plane;             // elements between consecutive direction planes
+  const InstDev* __restrict__ inst;
+  const WorkItem* __restrict__ items;
+  int n_items;
+  int xcd_swizzle;
+  int* queue;                  // [0] next ticket, [1] finished workgroups (persistent launches)
+  int* err;                    // sticky device error bits: [0] any instance, [1 + k] instance k
+  double* mrho;                // moments outputs (moments launches only), instance-local [nr][nz]
+  double* muz;
+  double* mur;
+};
+
+struct RowRef {
+  int inst, row;
+};
+
+template <typename R>
+hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool persist, int grid,
+                          hipStream_t st);
+template <typename R>
+hipError_t launch_unstream(R* fout, long long P, int nz, int nr, int bc_top, double rho_ref,
+                           const double* rho0,
+                           const double* uz0, const double* ur0, const double* f0, hipStream_t st);
+template <typename R>
+hipError_t launch_export(const R* fin, long long P, int nz, int nr, int bc_top, double rho_ref,
+                         double* out, hipStream_t st);
+template <typename R>
+hipError_t launch_rows(int K, const R* fin, long long P, const InstDev* inst, const RowRef* rows,
+                       int nrows, const double* geo, double* part, hipStream_t st);
+hipError_t launch_finish(int K, const double* part, const int* row_start, const InstDev* inst, int n,
+                         double* out, hipStream_t st);
+
+}  // namespace lbm

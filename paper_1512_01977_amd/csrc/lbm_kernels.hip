@@ -1,0 +1,654 @@
+// HIP kernels of the axisymmetric multiphase lattice Boltzmann step (arXiv:1512.01977)
+// for gfx950.  See lbm_axi.h for conventions.
+//
+// Fused step kernel ("sweep").  One workgroup of W lanes owns a strip of W - 12
+// output columns (z, contiguous in memory) plus a 6-column halo on each side,
+// and walks up the rows (r) of one segment.  Every iteration t advances four
+// pipeline stages that lag each other by two rows:
+//   A (row t)    pull-gather the 9 populations with the wall maps, moments rho and
+//                j, EOS in FP64: P_k, kappa = dP_k/drho, psi = sqrt(rho/3 - P_k)
+//   B (row t-2)  D_z psi, D_r psi (eq. fifthorderaccuratefinitedifference) and
+//                the Kupershtokh force F_K (eq. kupershtokhforcing)
+//   C (row t-4)  D_rr psi = D_r(D_r psi), D_rz psi = D_r(D_z psi), F_axis
+//                (eq. multiphasecorrections), F, physical velocity u = (j + F/2)/rho
+//   D (row t-6)  D_r u_z, D_z u_r, D_r u_r, H and h_i (eq. axihz), exact-difference
+//                forcing + BGK (eq. lbm), store the post-collision populations
+// Each stage's stencil input lives in a 5-row LDS ring (psi, D_z psi, D_r psi,
+// u_z, u_r); values a stage needs only at its own node travel in registers.
+// Ghost rows across the axis and the outer wall are written into the rings by the
+// producing stage with the field's mirror parity, so the stencils never branch.
+// Nothing but the populations touches HBM: one read and one write per node.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lbm_axi_internal.h"
+
+namespace lbm {
+
+constexpr int RD = 5;  // ring depth: a radius-2 stencil reads 5 consecutive rows
+enum { R_PSI = 0, R_DZ = 1, R_DR = 2, R_UZ = 3, R_UR = 4, NRING = 5 };
+enum { ERR_BIT_DOMAIN = 1, ERR_BIT_NONFINITE = 2 };
+
+__device__ __forceinline__ int wrapi(int x, int n) {
+  int r = x % n;
+  return r < 0 ? r + n : r;
+}
+__device__ __forceinline__ int slot(int x) {
+  int r = x % RD;
+  return r < 0 ? r + RD : r;
+}
+
+// P_k and kappa = dP_k/drho in FP64 (Sec. 2.3; Carnahan-Starling in the same slot).
+__device__ __forceinline__ void eos_dev(const InstDev& I, double rho, double& P, double& kap) {
+  if (I.eos == LBM_EOS_CS) {
+    const double e = 0.25 * I.b * rho;
+    const double im = 1.0 / (1.0 - e);
+    const double im3 = im * im * im;
+    const double num = 1.0 + e * (1.0 + e * (1.0 - e));
+    const double dnum = 1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)));
+    P = I.lam * (I.R * I.T * rho * num * im3 - I.a * rho * rho);
+    kap = I.lam * (I.R * I.T * dnum * im3 * im - 2.0 * I.a * rho);
+  } else if (I.eos == LBM_EOS_VDW) {
+    const double id = 1.0 / (3.0 - rho);
+    P = I.lam * (8.0 * rho * I.T * id - 3.0 * rho * rho);
+    kap = I.lam * (24.0 * I.T * id * id - 6.0 * rho);
+  } else {
+    P = rho / 3.0;
+    kap = 1.0 / 3.0;
+  }
+}
+
+__device__ __forceinline__ bool in_domain(const InstDev& I, double rho) {
+  if (I.eos == LBM_EOS_CS) return rho < 4.0 / I.b;
+  if (I.eos == LBM_EOS_VDW) return rho < 3.0;
+  return true;
+}
+
+// Post-streaming populations of node (col, x) pulled from the post-collision
+// planes fin: f_i(x) = f*_i(x - c_i), with mid-grid specular reflection at the axis,
+// specular (free slip) or half-way bounce-back (no slip) at r = nr, periodic z.
+// cm, c0, cp are the wrapped columns k-1, k, k+1.
+template <typename R>
+__device__ __forceinline__ void gather(const R* __restrict__ f, long long P, int nz, int nr, int bc_top,
+                                       int x, int cm, int c0, int cp, R o[9]) {
+  const R* r0 = f + (long long)x * nz;
+  o[0] = r0[c0];
+  o[1] = r0[P + cm];
+  o[3] = r0[3 * P + cp];
+  if (x > 0) {
+    const R* rm = r0 - nz;  // row x-1 feeds the directions with c_r = +1
+    o[2] = rm[2 * P + c0];
+    o[5] = rm[5 * P + cm];
+    o[6] = rm[6 * P + cp];
+  } else {  // axis: (c_z, +1) arrives from (c_z, -1) leaving node (k - c_z, 0)
+    o[2] = r0[4 * P + c0];
+    o[5] = r0[8 * P + cm];
+    o[6] = r0[7 * P + cp];
+  }
+  if (x < nr - 1) {
+    const R* rp = r0 + nz;  // row x+1 feeds the directions with c_r = -1
+    o[4] = rp[4 * P + c0];
+    o[7] = rp[7 * P + cp];
+    o[8] = rp[8 * P + cm];
+  } else if (bc_top == LBM_TOP_FREE_SLIP) {  // (c_z, -1) from (c_z, +1) at (k - c_z, nr-1)
+    o[4] = r0[2 * P + c0];
+    o[7] = r0[6 * P + cp];
+    o[8] = r0[5 * P + cm];
+  } else {  // bounce-back: (-c_z, -1) from (c_z, +1) of the same node
+    o[4] = r0[2 * P + c0];
+    o[7] = r0[5 * P + c0];
+    o[8] = r0[6 * P + c0];
+  }
+}
+
+// Equilibrium of Sec. 2.1 (c_s^2 = 1/3) relative to the storage shift:
+// E_i(rho, u) - w_i rho_ref = w_i [(rho - rho_ref) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)],
+// with sg = rho - rho_ref as summed from the shifted populations.
+template <typename R>
+__device__ __forceinline__ void shifted_equilibrium(R rho, R sg, R uz, R ur, R e[9]) {
+  const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
+  const R m = R(-1.5) * (uz * uz + ur * ur);
+  auto E = [&](R w, R cu) { return w * (sg + rho * (m + R(3.0) * cu + R(4.5) * cu * cu)); };
+  e[0] = w0 * (sg + rho * m);
+  e[1] = E(w1, uz);
+  e[2] = E(w1, ur);
+  e[3] = E(w1, -uz);
+  e[4] = E(w1, -ur);
+  e[5] = E(w2, uz + ur);
+  e[6] = E(w2, -uz + ur);
+  e[7] = E(w2, -uz - ur);
+  e[8] = E(w2, uz - ur);
+}
+
+// E_i(rho, u + du) - E_i(rho, u) = w_i rho [3 c.du + 4.5 (c.du)(c.(2u + du)) - 1.5 du.(2u + du)]
+template <typename R>
+__device__ __forceinline__ void edm_increment(R rho, R uz, R ur, R dz, R dr, R d[9]) {
+  const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
+  const R sz = R(2) * uz + dz, sr = R(2) * ur + dr;
+  const R m = R(-1.5) * (dz * sz + dr * sr);
+  auto D = [&](R w, R cd, R cs) { return w * rho * (m + R(3.0) * cd + R(4.5) * cd * cs); };
+  d[0] = w0 * rho * m;
+  d[1] = D(w1, dz, sz);
+  d[2] = D(w1, dr, sr);
+  d[3] = D(w1, -dz, -sz);
+  d[4] = D(w1, -dr, -sr);
+  d[5] = D(w2, dz + dr, sz + sr);
+  d[6] = D(w2, -dz + dr, -sz + sr);
+  d[7] = D(w2, -dz - dr, -sz - sr);
+  d[8] = D(w2, dz - dr, sz - sr);
+}
+
+// Stencil readers over a ring: V(row slot, z offset).
+template <typename R, int W>
+struct RingView {
+  R (*ring)[W + 4];  // [RD][W + 4]
+  int l;             // lane + 2
+  __device__ __forceinline__ R operator()(int s, int dz) const { return ring[s][l + dz]; }
+};
+
+// D_z g at the row with slots (m2, m1, s0, p1, p2) for rows x-2..x+2, in the direction
+// order 1, 3, 5, 6, 7, 8 of the stencil sum.
+template <typename R, int W>
+__device__ __forceinline__ R stencil_dz(const RingView<R, W>& v, int m2, int m1, int s0, int p1, int p2) {
+  R s = R(8) * v(s0, 1) - v(s0, 2);
+  s -= R(8) * v(s0, -1) - v(s0, -2);
+  s += R(8) * v(p1, 1) - v(p2, 2);
+  s -= R(8) * v(p1, -1) - v(p2, -2);
+  s -= R(8) * v(m1, -1) - v(m2, -2);
+  s += R(8) * v(m1, 1) - v(m2, 2);
+  return s / R(36);
+}
+
+// D_r g, directions 2, 4, 5, 6, 7, 8.
+template <typename R, int W>
+__device__ __forceinline__ R stencil_dr(const RingView<R, W>& v, int m2, int m1, int s0, int p1, int p2) {
+  R s = R(8) * v(p1, 0) - v(p2, 0);
+  s -= R(8) * v(m1, 0) - v(m2, 0);
+  s += R(8) * v(p1, 1) - v(p2, 2);
+  s += R(8) * v(p1, -1) - v(p2, -2);
+  s -= R(8) * v(m1, -1) - v(m2, -2);
+  s -= R(8) * v(m1, 1) - v(m2, 2);
+  return s / R(36);
+}
+
+template <typename R, int W, bool MOMENTS>
+__device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem wi, R (*ring)[RD][W + 4],
+                                         int lane) {
+  const InstDev I = g.inst[wi.inst];
+  const int nz = I.nz, nr = I.nr;
+  const int col = wrapi(wi.k0 - 6 + lane, nz);
+  const int cm = wrapi(col - 1, nz), cp = wrapi(col + 1, nz);
+  const bool out_lane = lane >= 6 && lane < 6 + wi.ncols;
+  const R* __restrict__ fin = g.fin + I.base;
+  R* __restrict__ fout = g.fout + I.base;
+  const long long P = g.plane;
+  const int s = wi.s, e = wi.e;
+  const int a_lo = max(0, s - 6), a_hi = min(nr, e + 6);
+  const int b_lo = max(0, s - 4), b_hi = min(nr, e + 4);
+  const int c_lo = max(0, s - 2), c_hi = min(nr, e + 2);
+  const R A = R(I.A), omega = R(I.omega), nu = R(I.nu), gzf = R(I.gz);
+  const R top_uz = I.bc_top == LBM_TOP_NO_SLIP ? R(-1) : R(1);
+  const R psi_ref = R(I.psi_ref), pr2 = R(2.0 * I.psi_ref);
+  const int l2 = lane + 2;
+  const RingView<R, W> Vpsi{ring[R_PSI], l2}, Vdz{ring[R_DZ], l2}, Vdr{ring[R_DR], l2};
+  const RingView<R, W> Vuz{ring[R_UZ], l2}, Vur{ring[R_UR], l2};
+
+  // node values travelling from stage A to stage C (ages 0..4) and from B/C onward
+  R rho_d[5], sg_d[5], jz_d[5], jr_d[5], kap_d[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) rho_d[q] = sg_d[q] = jz_d[q] = jr_d[q] = kap_d[q] = R(0);
+  R fk0z = 0, fk0r = 0, fk1z = 0, fk1r = 0, fk2z = 0, fk2r = 0;
+  R fc0z = 0, fc0r = 0, fc1z = 0, fc1r = 0, fc2z = 0, fc2r = 0;
+  int bad = 0;
+
+  for (int t = a_lo; t < e + 6; ++t) {
+#pragma unroll
+    for (int q = 4; q > 0; --q) {
+      rho_d[q] = rho_d[q - 1];
+      sg_d[q] = sg_d[q - 1];
+      jz_d[q] = jz_d[q - 1];
+      jr_d[q] = jr_d[q - 1];
+      kap_d[q] = kap_d[q - 1];
+    }
+    fk2z = fk1z; fk2r = fk1r; fk1z = fk0z; fk1r = fk0r;
+    fc2z = fc1z; fc2r = fc1r; fc1z = fc0z; fc1r = fc0r;
+
+    // ------------------------------------------------------------------ A: row t
+    {
+      const int x = t;
+      if (x >= a_lo && x < a_hi) {
+        R f[9];
+        gather<R>(fin, P, nz, nr, I.bc_top, x, cm, col, cp, f);
+        const R sg = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+        const R jz = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+        const R jr = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+        const double rd = I.rho_ref + (double)sg;  // rho in FP64 for the EOS
+        const R rho = R(rd);
+        double Pk, kap;
+        eos_dev(I, rd, Pk, kap);
+        double psi2 = I.eos == LBM_EOS_IDEAL ? 0.0 : rd / 3.0 - Pk;
+        if (!(rd > 0.0) || !in_domain(I, rd) || !(psi2 >= 0.0)) bad |= ERR_BIT_DOMAIN;
+        if (!isfinite(rd) || !isfinite(jz) || !isfinite(jr)) bad |= ERR_BIT_NONFINITE;
+        const R psi = R(sqrt(fmax(psi2, 0.0)) - I.psi_ref);  // stored relative to psi_ref
+        ring[R_PSI][slot(x)][l2] = psi;
+        if (x == 0) ring[R_PSI][slot(-1)][l2] = psi;  // psi is even across the axis
+        if (x == 1) ring[R_PSI][slot(-2)][l2] = psi;
+        rho_d[0] = rho;
+        sg_d[0] = sg;
+        jz_d[0] = jz;
+        jr_d[0] = jr;
+        kap_d[0] = R(kap);
+      } else if (a_hi == nr && (x == nr || x == nr + 1)) {
+        ring[R_PSI][slot(x)][l2] = ring[R_PSI][slot(2 * nr - 1 - x)][l2];  // even at the wall
+      }
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------------ B: row t-2
+    {
+      const int x = t - 2;
+      if (x >= b_lo && x < b_hi) {
+        const int m2 = slot(x - 2), m1 = slot(x - 1), s0 = slot(x), p1 = slot(x + 1), p2 = slot(x + 2);
+        const R dz = stencil_dz<R, W>(Vpsi, m2, m1, s0, p1, p2);
+        const R dr = stencil_dr<R, W>(Vpsi, m2, m1, s0, p1, p2);
+        // F_K = 6 [A sum_i w_i psi_i^2 c_i + (1 - 2A) psi sum_i w_i psi_i c_i], i = 1, 2, ..., 8
+        const R w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
+        const R q1 = Vpsi(s0, 1), q2 = Vpsi(p1, 0), q3 = Vpsi(s0, -1), q4 = Vpsi(m1, 0);
+        const R q5 = Vpsi(p1, 1), q6 = Vpsi(p1, -1), q7 = Vpsi(m1, -1), q8 = Vpsi(m1, 1);
+        const R s1z = w1 * q1 - w1 * q3 + w2 * q5 - w2 * q6 - w2 * q7 + w2 * q8;
+        const R s1r = w1 * q2 - w1 * q4 + w2 * q5 + w2 * q6 - w2 * q7 - w2 * q8;
+        // psi_i^2 = psi_ref^2 + d_i (2 psi_ref + d_i); the constant cancels in sum_i w_i c_i
+        const R t1 = q1 * (pr2 + q1), t2 = q2 * (pr2 + q2), t3 = q3 * (pr2 + q3), t4 = q4 * (pr2 + q4);
+        const R t5 = q5 * (pr2 + q5), t6 = q6 * (pr2 + q6), t7 = q7 * (pr2 + q7), t8 = q8 * (pr2 + q8);
+        const R s2z = w1 * t1 - w1 * t3 + w2 * t5 - w2 * t6 - w2 * t7 + w2 * t8;
+        const R s2r = w1 * t2 - w1 * t4 + w2 * t5 + w2 * t6 - w2 * t7 - w2 * t8;
+        const R psi = psi_ref + Vpsi(s0, 0);
+        fk0z = R(6) * (A * s2z + (R(1) - R(2) * A) * psi * s1z);
+        fk0r = R(6) * (A * s2r + (R(1) - R(2) * A) * psi * s1r);
+        ring[R_DZ][s0][l2] = dz;
+        ring[R_DR][s0][l2] = dr;
+        if (x == 0) { ring[R_DZ][slot(-1)][l2] = dz; ring[R_DR][slot(-1)][l2] = -dr; }
+        if (x == 1) { ring[R_DZ][slot(-2)][l2] = dz; ring[R_DR][slot(-2)][l2] = -dr; }
+      } else if (b_hi == nr && (x == nr || x == nr + 1)) {
+        const int m = slot(2 * nr - 1 - x), sx = slot(x);
+        ring[R_DZ][sx][l2] = ring[R_DZ][m][l2];   // D_z psi even at the wall
+        ring[R_DR][sx][l2] = -ring[R_DR][m][l2];  // D_r psi odd
+      }
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------------ C: row t-4
+    {
+      const int x = t - 4;
+      if (x >= c_lo && x < c_hi) {
+        const int m2 = slot(x - 2), m1 = slot(x - 1), s0 = slot(x), p1 = slot(x + 1), p2 = slot(x + 2);
+        const R rho = rho_d[4], jz = jz_d[4], jr = jr_d[4], kap = kap_d[4];
+        R fz = fk2z, fr = fk2r;
+        if (I.axisym) {
+          const R drr = stencil_dr<R, W>(Vdr, m2, m1, s0, p1, p2);
+          const R drz = stencil_dr<R, W>(Vdz, m2, m1, s0, p1, p2);
+          const R psi = psi_ref + Vpsi(s0, 0), dz = Vdz(s0, 0), dr = Vdr(s0, 0);
+          const R r = R(x) + R(0.5);
+          const R K = I.faxis_sound ? R(1.0 / 9.0) : kap * kap;
+          const R gz_ = drz / r;
+          const R gr_ = drr / r - dr / (r * r);
+          fz += R(3) * K * (psi * gz_ + R(6) * A / r * dr * dz);
+          fr += R(3) * K * (psi * gr_ + R(6) * A / r * dr * dr);
+        }
+        fz += gzf;
+        const R uz = (jz + R(0.5) * fz) / rho;
+        const R ur = (jr + R(0.5) * fr) / rho;
+        fc0z = fz;
+        fc0r = fr;
+        ring[R_UZ][s0][l2] = uz;
+        ring[R_UR][s0][l2] = ur;
+        if (x == 0) { ring[R_UZ][slot(-1)][l2] = uz; ring[R_UR][slot(-1)][l2] = -ur; }
+        if (x == 1) { ring[R_UZ][slot(-2)][l2] = uz; ring[R_UR][slot(-2)][l2] = -ur; }
+        if (MOMENTS && out_lane && x >= s && x < e) {
+          const long long o = (long long)x * nz + col;
+          g.mrho[o] = (double)rho;
+          g.muz[o] = (double)uz;
+          g.mur[o] = (double)ur;
+        }
+      } else if (c_hi == nr && (x == nr || x == nr + 1)) {
+        const int m = slot(2 * nr - 1 - x), sx = slot(x);
+        ring[R_UZ][sx][l2] = top_uz * ring[R_UZ][m][l2];
+        ring[R_UR][sx][l2] = -ring[R_UR][m][l2];
+      }
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------------ D: row t-6
+    if (!MOMENTS) {
+      const int x = t - 6;
+      if (x >= s && x < e) {
+        const int m2 = slot(x - 2), m1 = slot(x - 1), s0 = slot(x), p1 = slot(x + 1), p2 = slot(x + 2);
+        R f[9];
+        gather<R>(fin, P, nz, nr, I.bc_top, x, cm, col, cp, f);
+        const R sg = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+        const R jz = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+        const R jr = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+        const R rho = R(I.rho_ref + (double)sg);
+        const R Fz = fc2z, Fr = fc2r;
+        R h[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) h[i] = R(0);
+        if (I.axisym) {
+          const R uz = Vuz(s0, 0), ur = Vur(s0, 0);
+          const R druz = stencil_dr<R, W>(Vuz, m2, m1, s0, p1, p2);
+          const R dzur = stencil_dz<R, W>(Vur, m2, m1, s0, p1, p2);
+          const R drur = stencil_dr<R, W>(Vur, m2, m1, s0, p1, p2);
+          const R r = R(x) + R(0.5);
+          const R mu = rho * nu;
+          // eq. (axihz); H_r carries -u_r/r so that sum_i c_ir h_i supplies C_r = 2 mu d/dr(u_r/r)
+          const R Hz = (mu * (druz + dzur) - rho * ur * uz) / r;
+          const R Hr = (R(2) * mu * (drur - ur / r) - rho * ur * ur) / r;
+          const R m0 = -rho * ur / r;
+          const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
+          const R hz3 = R(3) * Hz, hr3 = R(3) * Hr;
+          h[0] = w0 * m0;
+          h[1] = w1 * (m0 + hz3);
+          h[2] = w1 * (m0 + hr3);
+          h[3] = w1 * (m0 - hz3);
+          h[4] = w1 * (m0 - hr3);
+          h[5] = w2 * (m0 + (hz3 + hr3));
+          h[6] = w2 * (m0 + (-hz3 + hr3));
+          h[7] = w2 * (m0 + (-hz3 - hr3));
+          h[8] = w2 * (m0 + (hz3 - hr3));
+        }
+        const R ubz = jz / rho, ubr = jr / rho;
+        R e0[9], de[9];
+        // E_i(rho, u_b) - w_i rho_ref, and the exact-difference increment
+        // E_i(rho, u_b + F/rho) - E_i(rho, u_b), both in difference form
+        shifted_equilibrium<R>(rho, sg, ubz, ubr, e0);
+        edm_increment<R>(rho, ubz, ubr, Fz / rho, Fr / rho, de);
+        if (out_lane) {
+          R* o = fout + (long long)x * nz + col;
+#pragma unroll
+          for (int i = 0; i < 9; ++i) o[i * P] = f[i] + omega * (e0[i] - f[i]) + de[i] + h[i];
+        }
+      }
+    }
+  }
+  if (bad) {
+    atomicOr(g.err, bad);                 // any instance
+    atomicOr(g.err + 1 + wi.inst, bad);   // this instance
+  }
+}
+
+__device__ __forceinline__ int xcd_map(int b, int G) {
+  // Hardware hands workgroup b to XCD b % 8; give each XCD one contiguous run of items.
+  const int xcd = b & 7, pos = b >> 3;
+  const int q = G >> 3, rem = G & 7;
+  return xcd < rem ? xcd * (q + 1) + pos : rem * (q + 1) + (xcd - rem) * q + pos;
+}
+
+template <typename R, int W, bool MOMENTS, bool PERSIST>
+__global__ void __launch_bounds__(W) k_sweep(SweepArgs<R> g) {
+  __shared__ R ring[NRING][RD][W + 4];
+  __shared__ int s_ticket;
+  const int lane = threadIdx.x;
+  if (!PERSIST) {
+    const int b = (int)blockIdx.x;
+    const int item = g.xcd_swizzle ? xcd_map(b, (int)gridDim.x) : b;
+    if (item < g.n_items) run_item<R, W, MOMENTS>(g, g.items[item], ring, lane);
+    return;
+  }
+  for (;;) {
+    if (lane == 0) s_ticket = atomicAdd(&g.queue[0], 1);
+    __syncthreads();
+    const int item = s_ticket;
+    __syncthreads();
+    if (item >= g.n_items) break;
+    run_item<R, W, MOMENTS>(g, g.items[item], ring, lane);
+  }
+  if (lane == 0) {
+    // The last workgroup out rewinds the queue for the next launch (no memset needed,
+    // which keeps graph replays free of memset nodes).
+    const int done = atomicAdd(&g.queue[1], 1);
+    if (done == (int)gridDim.x - 1) {
+      atomicExch(&g.queue[0], 0);
+      atomicExch(&g.queue[1], 0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------- init / checkpoint
+
+__device__ __constant__ int c_cz[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ __constant__ int c_cr[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ __constant__ int c_mirror_r[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};  // (c_z, c_r) -> (c_z, -c_r)
+__device__ __constant__ int c_opposite[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};  // c -> -c
+
+// Post-collision planes whose streaming yields the given post-streaming state f0:
+// the inverse of the pull map.  f0 is either a double [9][nr][nz] array, or (when
+// f0 == nullptr) the equilibrium E(rho0, u0) of the initial fields (Sec. 2.1).
+template <typename R>
+__global__ void k_unstream(R* __restrict__ fout, long long P, int nz, int nr, int bc_top, double rho_ref,
+                           const double* __restrict__ rho0, const double* __restrict__ uz0,
+                           const double* __restrict__ ur0, const double* __restrict__ f0) {
+  const double wgt[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                         1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+  const long long n = (long long)nz * nr;
+  for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < n;
+       id += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(id % nz), j = (int)(id / nz);
+    for (int i = 0; i < 9; ++i) {
+      int tk = k + c_cz[i], tj = j + c_cr[i], ti = i;
+      if (tj < 0) {
+        tj = 0;
+        ti = c_mirror_r[i];
+      } else if (tj >= nr) {
+        tj = nr - 1;
+        if (bc_top == LBM_TOP_NO_SLIP) {
+          tk = k;
+          ti = c_opposite[i];
+        } else {
+          ti = c_mirror_r[i];
+        }
+      }
+      tk = wrapi(tk, nz);
+      const long long tn = (long long)tj * nz + tk;
+      double v;
+      if (f0) {
+        v = f0[ti * n + tn] - wgt[ti] * rho_ref;
+      } else {
+        double e[9];
+        shifted_equilibrium<double>(rho0[tn], rho0[tn] - rho_ref, uz0 ? uz0[tn] : 0.0,
+                                    ur0 ? ur0[tn] : 0.0, e);
+        v = e[ti];
+      }
+      fout[i * P + id] = R(v);
+    }
+  }
+}
+
+template <typename R>
+__global__ void k_export(const R* __restrict__ fin, long long P, int nz, int nr, int bc_top, double rho_ref,
+                         double* __restrict__ out) {
+  const double wgt[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                         1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+  const long long n = (long long)nz * nr;
+  for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < n;
+       id += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(id % nz), j = (int)(id / nz);
+    R f[9];
+    gather<R>(fin, P, nz, nr, bc_top, j, wrapi(k - 1, nz), k, wrapi(k + 1, nz), f);
+    for (int i = 0; i < 9; ++i) out[i * n + id] = (double)f[i] + wgt[i] * rho_ref;
+  }
+}
+
+// ---------------------------------------------------------------------------- reductions
+
+// Fixed-shape FP64 block reduction (64-lane wavefronts, then LDS): deterministic.
+template <int NT, int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double (*sm)[K]) {
+#pragma unroll
+  for (int q = 0; q < K; ++q)
+    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0)
+    for (int q = 0; q < K; ++q) sm[w][q] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < K; ++q) {
+      double s = 0.0;
+      for (int i = 0; i < NT / 64; ++i) s += sm[i][q];
+      v[q] = s;
+    }
+  }
+}
+
+
+// Per row: K = 1: sum_k rho; K = 4: (sum P_k, count) inside r_in and (sum P_k, count) beyond r_out.
+template <typename R, int K>
+__global__ void __launch_bounds__(256) k_rows(const R* __restrict__ fin, long long P,
+                                              const InstDev* __restrict__ inst,
+                                              const RowRef* __restrict__ rows,
+                                              const double* __restrict__ geo, double* __restrict__ part) {
+  __shared__ double sm[4][K];
+  const RowRef rr = rows[blockIdx.x];
+  const InstDev I = inst[rr.inst];
+  const int nz = I.nz, j = rr.row;
+  const R* f = fin + I.base;
+  double acc[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) acc[q] = 0.0;
+  const double rj = j + 0.5;
+  for (int k = threadIdx.x; k < nz; k += 256) {
+    R o[9];
+    gather<R>(f, P, nz, I.nr, I.bc_top, j, wrapi(k - 1, nz), k, wrapi(k + 1, nz), o);
+    const R sg = o[0] + o[1] + o[2] + o[3] + o[4] + o[5] + o[6] + o[7] + o[8];
+    const double rho = I.rho_ref + (double)sg;
+    if (K == 1) {
+      acc[0] += rho;
+    } else {
+      const double zc = geo[3 * rr.inst], rin = geo[3 * rr.inst + 1], rout = geo[3 * rr.inst + 2];
+      double Pk, kap;
+      eos_dev(I, rho, Pk, kap);
+      const double d = sqrt((k - zc) * (k - zc) + rj * rj);
+      if (d < rin) {
+        acc[0] += Pk;
+        acc[1] += 1.0;
+      }
+      if (d > rout) {
+        acc[2] += Pk;
+        acc[3] += 1.0;
+      }
+    }
+  }
+  block_sum<256, K>(acc, sm);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < K; ++q) part[(long long)blockIdx.x * K + q] = acc[q];
+}
+
+// Per instance: combine its rows' partials in a fixed order.
+template <int K>
+__global__ void __launch_bounds__(256) k_finish(const double* __restrict__ part,
+                                                const int* __restrict__ row_start,
+                                                const InstDev* __restrict__ inst, double* __restrict__ out) {
+  __shared__ double sm[4][K];
+  const int n = blockIdx.x;
+  const int r0 = row_start[n], r1 = row_start[n + 1];
+  double acc[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) acc[q] = 0.0;
+  for (int r = r0 + threadIdx.x; r < r1; r += 256) {
+    if (K == 1) {
+      const double rj = (r - r0) + 0.5;
+      acc[0] += 2.0 * M_PI * rj * part[r];
+    } else {
+      for (int q = 0; q < K; ++q) acc[q] += part[(long long)r * K + q];
+    }
+  }
+  block_sum<256, K>(acc, sm);
+  if (threadIdx.x == 0) {
+    if (K == 1)
+      out[n] = acc[0];
+    else
+      out[n] = (acc[1] > 0.0 && acc[3] > 0.0) ? acc[0] / acc[1] - acc[2] / acc[3] : __builtin_nan("");
+  }
+  (void)inst;
+}
+
+// ---------------------------------------------------------------------------- host-side launchers
+
+template <typename R, int W, bool MOMENTS, bool PERSIST>
+static hipError_t launch_sweep(const SweepArgs<R>& g, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_sweep<R, W, MOMENTS, PERSIST>), dim3(grid), dim3(W), 0, st, g);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool persist, int grid,
+                          hipStream_t st) {
+#define LBM_CASE(WW)                                                          \
+  case WW:                                                                    \
+    if (moments) return launch_sweep<R, WW, true, false>(g, grid, st);        \
+    if (persist) return launch_sweep<R, WW, false, true>(g, grid, st);        \
+    return launch_sweep<R, WW, false, false>(g, grid, st);
+  switch (width) {
+    LBM_CASE(64)
+    LBM_CASE(128)
+    LBM_CASE(256)
+    default:
+      break;
+  }
+#undef LBM_CASE
+  return hipErrorInvalidValue;
+}
+
+template hipError_t sweep_dispatch<float>(const SweepArgs<float>&, int, bool, bool, int, hipStream_t);
+template hipError_t sweep_dispatch<double>(const SweepArgs<double>&, int, bool, bool, int, hipStream_t);
+
+template <typename R>
+hipError_t launch_unstream(R* fout, long long P, int nz, int nr, int bc_top, double rho_ref, const double* rho0,
+                           const double* uz0, const double* ur0, const double* f0, hipStream_t st) {
+  const long long n = (long long)nz * nr;
+  const int grid = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+  hipLaunchKernelGGL((k_unstream<R>), dim3(grid), dim3(256), 0, st, fout, P, nz, nr, bc_top, rho_ref, rho0,
+                     uz0, ur0, f0);
+  return hipGetLastError();
+}
+template hipError_t launch_unstream<float>(float*, long long, int, int, int, double, const double*,
+                                           const double*, const double*, const double*, hipStream_t);
+template hipError_t launch_unstream<double>(double*, long long, int, int, int, double, const double*,
+                                            const double*, const double*, const double*, hipStream_t);
+
+template <typename R>
+hipError_t launch_export(const R* fin, long long P, int nz, int nr, int bc_top, double rho_ref, double* out,
+                         hipStream_t st) {
+  const long long n = (long long)nz * nr;
+  const int grid = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+  hipLaunchKernelGGL((k_export<R>), dim3(grid), dim3(256), 0, st, fin, P, nz, nr, bc_top, rho_ref, out);
+  return hipGetLastError();
+}
+template hipError_t launch_export<float>(const float*, long long, int, int, int, double, double*, hipStream_t);
+template hipError_t launch_export<double>(const double*, long long, int, int, int, double, double*,
+                                          hipStream_t);
+
+template <typename R>
+hipError_t launch_rows(int K, const R* fin, long long P, const InstDev* inst, const RowRef* rows, int nrows,
+                       const double* geo, double* part, hipStream_t st) {
+  if (K == 1)
+    hipLaunchKernelGGL((k_rows<R, 1>), dim3(nrows), dim3(256), 0, st, fin, P, inst, rows, geo, part);
+  else
+    hipLaunchKernelGGL((k_rows<R, 4>), dim3(nrows), dim3(256), 0, st, fin, P, inst, rows, geo, part);
+  return hipGetLastError();
+}
+template hipError_t launch_rows<float>(int, const float*, long long, const InstDev*, const RowRef*, int,
+                                       const double*, double*, hipStream_t);
+template hipError_t launch_rows<double>(int, const double*, long long, const InstDev*, const RowRef*, int,
+                                        const double*, double*, hipStream_t);
+
+hipError_t launch_finish(int K, const double* part, const int* row_start, const InstDev* inst, int n,
+                         double* out, hipStream_t st) {
+  if (K == 1)
+    hipLaunchKernelGGL((k_finish<1>), dim3(n), dim3(256), 0, st, part, row_start, inst, out);
+  else
+    hipLaunchKernelGGL((k_finish<4>), dim3(n), dim3(256), 0, st, part, row_start, inst, out);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

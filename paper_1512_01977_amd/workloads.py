@@ -1,0 +1,113 @@
+"""Named synthetic workloads (the paper's validation set-ups, Sec. 3, at the sizes
+the benchmark and the tests use).  Parameters only: temperatures are set from
+T/T_c and initial densities from the Maxwell coexistence densities, both through
+the library's host EOS helpers; fields come from the seeded input module.
+
+Carnahan-Starling coefficients a = 1, b = 4, R = 1 throughout.  The pressure
+scale lambda and the mixing parameter A are the paper's own knobs (Sec. 2.3):
+lambda = 1 with A = 0 for the moderate-ratio workloads; lambda = 0.05 with
+A = -0.152 (the paper's coexistence value) for the ensemble and where the
+liquid/vapour density ratio reaches about 1e3: with lambda = 1 (or 0.1 for the
+larger low-temperature droplets) the state leaves the real-psi range within the
+first steps from a tanh start, in the CPU oracle as well.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import inputs
+from .lbm import EOS_CS, PREC_FP32, PREC_FP64, TOP_FREE_SLIP, TOP_NO_SLIP, Params
+from .lbm import lbm_axi_eos_coexistence, lbm_axi_eos_critical
+
+
+@dataclass
+class Workload:
+    name: str
+    params: list
+    rho0: list
+    precision: int
+    steps: int                      # steps of the full experiment (bench runs fewer)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nodes(self) -> int:
+        return int(sum(p.nz * p.nr for p in self.params))
+
+
+def cs_params(nz, nr, t_reduced, tau, lam=1.0, A=0.0, bc_top=TOP_FREE_SLIP, axisym=1) -> Params:
+    p = Params(nz=nz, nr=nr, tau=tau, eos=EOS_CS, eos_a=1.0, eos_b=4.0, eos_R=1.0, lam=lam, A=A,
+               axisym=axisym, bc_top=bc_top)
+    _, Tc, _ = lbm_axi_eos_critical(p)
+    p.T = t_reduced * Tc
+    return p
+
+
+def coexistence(p: Params):
+    rv, rl, _ = lbm_axi_eos_coexistence(p)
+    return rv, rl
+
+
+def static_droplet(precision=PREC_FP64) -> Workload:
+    """128 x 64, T/T_c = 0.8, tau = 1, R = 20 on the axis, width-5 tanh, noise 1e-4 (seed 1)."""
+    p = cs_params(128, 64, 0.8, 1.0)
+    rv, rl = coexistence(p)
+    rho = inputs.droplet(128, 64, rv, rl, 20.0, zc=64.0, width=5.0, noise=1e-4, seed=1)
+    return Workload("static_droplet_128x64", [p], [rho], precision, 2000,
+                    dict(R=20.0, zc=64.0, rho_v=rv, rho_l=rl))
+
+
+def mode2_droplet(precision=PREC_FP64, nz=1024, nr=512, radius=100.0) -> Workload:
+    """Mode-2 oscillation at density ratio ~1e3: T/T_c = 0.485, tau = 0.8, P2 amplitude 0.05."""
+    p = cs_params(nz, nr, 0.485, 0.8, lam=0.05, A=-0.152)
+    rv, rl = coexistence(p)
+    rho = inputs.droplet(nz, nr, rv, rl, radius, zc=nz / 2, width=10.0, eps=0.05, noise=1e-4,
+                         seed=2)
+    return Workload(f"mode2_droplet_{nz}x{nr}", [p], [rho], precision, 20000,
+                    dict(R=radius, zc=nz / 2, rho_v=rv, rho_l=rl))
+
+
+def density_wave(precision=PREC_FP64, nz=4096, nr=2048) -> Workload:
+    """Single-phase vapour at T/T_c = 0.9 with a radial cosine of amplitude 1e-2, wavelength
+    256, noise 1e-6 (seed 3), tau = 0.7, no-slip wall at r = nr (Sec. 3.3)."""
+    p = cs_params(nz, nr, 0.9, 0.7, bc_top=TOP_NO_SLIP)
+    rv, _ = coexistence(p)
+    rho = inputs.radial_wave(nz, nr, rv, amplitude=1e-2, wavelength=256.0, noise=1e-6, seed=3)
+    return Workload(f"density_wave_{nz}x{nr}", [p], [rho], precision, 10000, dict(rho_g=rv))
+
+
+def ensemble(precision=PREC_FP32, n=256, seed=151201977) -> Workload:
+    """Uneven droplet batch: nr ~ U{32..256}, nz = 2 nr, T/T_c ~ U[0.55, 0.9],
+    tau ~ U[0.7, 1.2], R = 0.3 nr, odd members with a P2 perturbation of 0.05.  (tau below 0.7
+    at T/T_c near 0.55 leaves the real-psi range during the first hundred steps, in the CPU
+    oracle as well.)"""
+    params, rhos, meta = [], [], []
+    for ins in inputs.ensemble(n=n, seed=seed, tau_lo=0.7):
+        p = cs_params(ins.nz, ins.nr, ins.t_reduced, ins.tau, lam=0.05, A=-0.152)
+        rv, rl = coexistence(p)
+        rhos.append(inputs.droplet(ins.nz, ins.nr, rv, rl, ins.radius, zc=ins.nz / 2, width=10.0,
+                                   eps=ins.eps, noise=1e-4, seed=ins.noise_seed))
+        params.append(p)
+        meta.append(dict(R=ins.radius, zc=ins.nz / 2, rho_v=rv, rho_l=rl))
+    return Workload(f"droplet_ensemble_{n}", params, rhos, precision, 2000, dict(members=meta))
+
+
+def large_droplet(precision=PREC_FP32, nz=16384, nr=8192, radius=2000.0) -> Workload:
+    """16384 x 8192 (134M nodes), ratio ~1e3 droplet R = 2000 with P2 amplitude 0.02,
+    tau = 0.8, noise 1e-4 (seed 5)."""
+    p = cs_params(nz, nr, 0.485, 0.8, lam=0.05, A=-0.152)
+    rv, rl = coexistence(p)
+    rho = inputs.droplet(nz, nr, rv, rl, radius, zc=nz / 2, width=10.0, eps=0.02, noise=1e-4,
+                         seed=5)
+    return Workload(f"large_droplet_{nz}x{nr}", [p], [rho], precision, 5000,
+                    dict(R=radius, zc=nz / 2, rho_v=rv, rho_l=rl))
+
+
+REGISTRY = {
+    "static": static_droplet,
+    "mode2": mode2_droplet,
+    "wave": density_wave,
+    "batch": ensemble,
+    "large": large_droplet,
+}

@@ -1,0 +1,48 @@
+"""Shared test workloads: parameter dictionaries turned into oracle or HIP-path
+parameter objects, and the seeded initial densities (from the input module).
+Holds none of the method's arithmetic."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as O
+from paper_1512_01977_amd import inputs
+
+_TC = {}
+
+
+def cs_tc(a=1.0, b=4.0, R=1.0):
+    key = (a, b, R)
+    if key not in _TC:
+        _TC[key] = O.critical(O.Params(nz=4, nr=4, eos=O.EOS_CS, eos_a=a, eos_b=b, eos_R=R))[1]
+    return _TC[key]
+
+
+def base(nz, nr, **kw):
+    d = dict(nz=nz, nr=nr, tau=1.0, eos=O.EOS_CS, T=0.8 * cs_tc(), eos_a=1.0, eos_b=4.0,
+             eos_R=1.0, lam=1.0, A=0.0, axisym=1, faxis_sound=0, bc_top=0, gz=0.0)
+    d.update(kw)
+    return d
+
+
+def oracle_params(d) -> O.Params:
+    return O.Params(**d)
+
+
+def gpu_params(d):
+    from paper_1512_01977_amd import lbm
+    return lbm.Params(**d)
+
+
+def droplet_rho(d, radius, eps=0.0, noise=1e-4, seed=1, width=5.0, zc=None):
+    if d["eos"] == O.EOS_IDEAL:
+        r = inputs.radial_wave(d["nz"], d["nr"], 1.0, amplitude=0.05, wavelength=d["nr"] / 1.5,
+                               noise=noise, seed=seed)
+        return r
+    rv, rl, _ = O.coexistence(oracle_params(d))
+    return inputs.droplet(d["nz"], d["nr"], rv, rl, radius, zc=zc, width=width, eps=eps,
+                          noise=noise, seed=seed)
+
+
+def rel_inf(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
