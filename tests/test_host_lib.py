@@ -1,0 +1,91 @@
+"""CPU checks of the HIP library's host side: it loads, exports every entry point its
+header declares, and its host EOS helpers agree with the independent oracle ones.
+No kernel is launched here."""
+import os
+import re
+
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(lbm_axi_\w+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1512_01977_amd import lbm
+    L = lbm.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(lbm.EXPORTS)
+
+
+def test_status_strings():
+    from paper_1512_01977_amd import lbm
+    L = lbm.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.lbm_axi_status_string(code)
+    assert L.lbm_axi_status_string(-4).startswith(b"equation-of-state")
+
+
+@pytest.mark.parametrize("t", [0.9, 0.8, 0.7, 0.55, 0.485])
+def test_host_cs_coexistence_matches_oracle(t):
+    from paper_1512_01977_amd import lbm
+    pl = lbm.Params(nz=4, nr=4, eos=lbm.EOS_CS)
+    rc, Tc, Pc = lbm.lbm_axi_eos_critical(pl)
+    orc, oTc, oPc = O.critical(O.Params(nz=4, nr=4, eos=O.EOS_CS))
+    assert Tc == pytest.approx(oTc, rel=1e-12)
+    assert rc == pytest.approx(orc, rel=1e-7)
+    pl.T = t * Tc
+    rv, rl, ps = lbm.lbm_axi_eos_coexistence(pl)
+    orv, orl, ops = O.coexistence(O.Params(nz=4, nr=4, eos=O.EOS_CS, T=t * oTc))
+    assert rv == pytest.approx(orv, rel=1e-9)
+    assert rl == pytest.approx(orl, rel=1e-12)
+    assert ps == pytest.approx(ops, rel=1e-9)
+
+
+@pytest.mark.parametrize("T", [0.9, 0.8, 0.7])
+def test_host_vdw_coexistence_matches_oracle(T):
+    from paper_1512_01977_amd import lbm
+    rv, rl, ps = lbm.lbm_axi_eos_coexistence(lbm.Params(nz=4, nr=4, eos=lbm.EOS_VDW, lam=0.01, T=T))
+    orv, orl, ops = O.coexistence(O.Params(nz=4, nr=4, eos=O.EOS_VDW, lam=0.01, T=T))
+    assert (rv, rl, ps) == (pytest.approx(orv, rel=1e-9), pytest.approx(orl, rel=1e-9),
+                            pytest.approx(ops, rel=1e-9))
+
+
+def test_host_helpers_reject_bad_input():
+    from paper_1512_01977_amd import lbm
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_axi_eos_coexistence(lbm.Params(nz=4, nr=4, eos=lbm.EOS_CS, T=1.0))  # above T_c
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_axi_eos_critical(lbm.Params(nz=4, nr=4, eos=lbm.EOS_IDEAL))
+
+
+def test_ensemble_workload_shape():
+    # The seeded ensemble: 256 members, nz = 2 nr, 12 889 106 nodes for seed 151201977.
+    from paper_1512_01977_amd import inputs
+    ens = inputs.ensemble()
+    assert len(ens) == 256
+    assert all(i.nz == 2 * i.nr and 32 <= i.nr <= 256 for i in ens)
+    assert sum(i.nz * i.nr for i in ens) == 12_889_106
+    assert all(0.55 <= i.t_reduced <= 0.9 for i in ens)
+
+
+def test_tuning_size_class_keys():
+    from paper_1512_01977_amd import lbm, tuning
+    a = tuning.size_class([lbm.Params(nz=16384, nr=8192)], 1)
+    b = tuning.size_class([lbm.Params(nz=16384, nr=8192)], 0)
+    c = tuning.size_class([lbm.Params(nz=64, nr=32)] * 256, 1)
+    assert a != b and a.startswith("gfx950:f32:single") and c.startswith("gfx950:f32:batch256")
