@@ -39,18 +39,33 @@ __device__ __forceinline__ int slot(int x) {
   return r < 0 ? r + RD : r;
 }
 
+// Reciprocals: hardware estimate refined by Newton steps (one for FP32, two for FP64),
+// within an ulp of 1/x; used instead of IEEE division on the hot path.
+__device__ __forceinline__ float recip(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  const float e = __builtin_fmaf(-x, r, 1.0f);
+  return __builtin_fmaf(r, e, r);
+}
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 // P_k and kappa = dP_k/drho in FP64 (Sec. 2.3; Carnahan-Starling in the same slot).
 __device__ __forceinline__ void eos_dev(const InstDev& I, double rho, double& P, double& kap) {
   if (I.eos == LBM_EOS_CS) {
     const double e = 0.25 * I.b * rho;
-    const double im = 1.0 / (1.0 - e);
+    const double im = recip(1.0 - e);
     const double im3 = im * im * im;
     const double num = 1.0 + e * (1.0 + e * (1.0 - e));
     const double dnum = 1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)));
     P = I.lam * (I.R * I.T * rho * num * im3 - I.a * rho * rho);
     kap = I.lam * (I.R * I.T * dnum * im3 * im - 2.0 * I.a * rho);
   } else if (I.eos == LBM_EOS_VDW) {
-    const double id = 1.0 / (3.0 - rho);
+    const double id = recip(3.0 - rho);
     P = I.lam * (8.0 * rho * I.T * id - 3.0 * rho * rho);
     kap = I.lam * (24.0 * I.T * id * id - 6.0 * rho);
   } else {
@@ -68,37 +83,106 @@ __device__ __forceinline__ bool in_domain(const InstDev& I, double rho) {
 // Post-streaming populations of node (col, x) pulled from the post-collision
 // planes fin: f_i(x) = f*_i(x - c_i), with mid-grid specular reflection at the axis,
 // specular (free slip) or half-way bounce-back (no slip) at r = nr, periodic z.
-// cm, c0, cp are the wrapped columns k-1, k, k+1.
+// cm, c0, cp are the wrapped columns k-1, k, k+1.  Row pointers are uniform across the
+// workgroup and the lane offsets are 32-bit, so the loads take a scalar base.
 template <typename R>
 __device__ __forceinline__ void gather(const R* __restrict__ f, long long P, int nz, int nr, int bc_top,
-                                       int x, int cm, int c0, int cp, R o[9]) {
+                                       int x, unsigned cm, unsigned c0, unsigned cp, R o[9]) {
   const R* r0 = f + (long long)x * nz;
+  const R* rm = x > 0 ? r0 - nz : r0;       // row x-1 feeds the directions with c_r = +1
+  const R* rp = x < nr - 1 ? r0 + nz : r0;  // row x+1 feeds the directions with c_r = -1
   o[0] = r0[c0];
-  o[1] = r0[P + cm];
-  o[3] = r0[3 * P + cp];
+  o[1] = (r0 + P)[cm];
+  o[3] = (r0 + 3 * P)[cp];
   if (x > 0) {
-    const R* rm = r0 - nz;  // row x-1 feeds the directions with c_r = +1
-    o[2] = rm[2 * P + c0];
-    o[5] = rm[5 * P + cm];
-    o[6] = rm[6 * P + cp];
+    o[2] = (rm + 2 * P)[c0];
+    o[5] = (rm + 5 * P)[cm];
+    o[6] = (rm + 6 * P)[cp];
   } else {  // axis: (c_z, +1) arrives from (c_z, -1) leaving node (k - c_z, 0)
-    o[2] = r0[4 * P + c0];
-    o[5] = r0[8 * P + cm];
-    o[6] = r0[7 * P + cp];
+    o[2] = (r0 + 4 * P)[c0];
+    o[5] = (r0 + 8 * P)[cm];
+    o[6] = (r0 + 7 * P)[cp];
   }
   if (x < nr - 1) {
-    const R* rp = r0 + nz;  // row x+1 feeds the directions with c_r = -1
-    o[4] = rp[4 * P + c0];
-    o[7] = rp[7 * P + cp];
-    o[8] = rp[8 * P + cm];
+    o[4] = (rp + 4 * P)[c0];
+    o[7] = (rp + 7 * P)[cp];
+    o[8] = (rp + 8 * P)[cm];
   } else if (bc_top == LBM_TOP_FREE_SLIP) {  // (c_z, -1) from (c_z, +1) at (k - c_z, nr-1)
-    o[4] = r0[2 * P + c0];
-    o[7] = r0[6 * P + cp];
-    o[8] = r0[5 * P + cm];
+    o[4] = (r0 + 2 * P)[c0];
+    o[7] = (r0 + 6 * P)[cp];
+    o[8] = (r0 + 5 * P)[cm];
   } else {  // bounce-back: (-c_z, -1) from (c_z, +1) of the same node
-    o[4] = r0[2 * P + c0];
-    o[7] = r0[5 * P + c0];
-    o[8] = r0[6 * P + c0];
+    o[4] = (r0 + 2 * P)[c0];
+    o[7] = (r0 + 5 * P)[c0];
+    o[8] = (r0 + 6 * P)[c0];
+  }
+}
+
+// The same pull map through raw buffer loads: three 128-bit descriptors, each covering
+// three consecutive direction planes of the instance, with the plane and the row as a
+// uniform byte offset and the column as a per-lane byte offset, so that no per-lane
+// address arithmetic is spent on the loads.  The host keeps 3 plane strides below 4 GiB.
+template <typename R>
+struct Planes {
+  __amdgpu_buffer_rsrc_t g[3];
+  unsigned pstride;  // bytes between consecutive planes
+};
+
+template <typename R>
+__device__ __forceinline__ Planes<R> make_planes(const R* base, long long P) {
+  Planes<R> p;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    p.g[i] = __builtin_amdgcn_make_buffer_rsrc(const_cast<R*>(base + 3 * i * P), (short)0, (int)0xffffffff,
+                                               (int)0x00020000);
+  p.pstride = (unsigned)(P * (long long)sizeof(R));
+  return p;
+}
+
+__device__ __forceinline__ float bload(float, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ double bload(double, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
+template <typename R>
+__device__ __forceinline__ R pload(const Planes<R>& pl, int q, unsigned voff, unsigned row_off) {
+  return bload(R(0), pl.g[q / 3], voff, row_off + (unsigned)(q % 3) * pl.pstride);
+}
+
+// bm, b0, bp: byte offsets of columns k-1, k, k+1 within a row.
+template <typename R>
+__device__ __forceinline__ void gather_b(const Planes<R>& pl, int nz, int nr, int bc_top, int x, unsigned bm,
+                                         unsigned b0, unsigned bp, R o[9]) {
+  const unsigned row = (unsigned)sizeof(R) * (unsigned)nz;
+  const unsigned s0 = (unsigned)x * row;
+  const unsigned sm = x > 0 ? s0 - row : s0;
+  const unsigned sp = x < nr - 1 ? s0 + row : s0;
+  o[0] = pload(pl, 0, b0, s0);
+  o[1] = pload(pl, 1, bm, s0);
+  o[3] = pload(pl, 3, bp, s0);
+  if (x > 0) {
+    o[2] = pload(pl, 2, b0, sm);
+    o[5] = pload(pl, 5, bm, sm);
+    o[6] = pload(pl, 6, bp, sm);
+  } else {
+    o[2] = pload(pl, 4, b0, s0);
+    o[5] = pload(pl, 8, bm, s0);
+    o[6] = pload(pl, 7, bp, s0);
+  }
+  if (x < nr - 1) {
+    o[4] = pload(pl, 4, b0, sp);
+    o[7] = pload(pl, 7, bp, sp);
+    o[8] = pload(pl, 8, bm, sp);
+  } else if (bc_top == LBM_TOP_FREE_SLIP) {
+    o[4] = pload(pl, 2, b0, s0);
+    o[7] = pload(pl, 6, bp, s0);
+    o[8] = pload(pl, 5, bm, s0);
+  } else {
+    o[4] = pload(pl, 2, b0, s0);
+    o[7] = pload(pl, 5, b0, s0);
+    o[8] = pload(pl, 6, b0, s0);
   }
 }
 
@@ -157,7 +241,7 @@ __device__ __forceinline__ R stencil_dz(const RingView<R, W>& v, int m2, int m1,
   s -= R(8) * v(p1, -1) - v(p2, -2);
   s -= R(8) * v(m1, -1) - v(m2, -2);
   s += R(8) * v(m1, 1) - v(m2, 2);
-  return s / R(36);
+  return s * R(1.0 / 36.0);
 }
 
 // D_r g, directions 2, 4, 5, 6, 7, 8.
@@ -169,7 +253,7 @@ __device__ __forceinline__ R stencil_dr(const RingView<R, W>& v, int m2, int m1,
   s += R(8) * v(p1, -1) - v(p2, -2);
   s -= R(8) * v(m1, -1) - v(m2, -2);
   s -= R(8) * v(m1, 1) - v(m2, 2);
-  return s / R(36);
+  return s * R(1.0 / 36.0);
 }
 
 template <typename R, int W, bool MOMENTS>
@@ -177,12 +261,13 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
                                          int lane) {
   const InstDev I = g.inst[wi.inst];
   const int nz = I.nz, nr = I.nr;
-  const int col = wrapi(wi.k0 - 6 + lane, nz);
-  const int cm = wrapi(col - 1, nz), cp = wrapi(col + 1, nz);
+  const unsigned col = (unsigned)wrapi(wi.k0 - 6 + lane, nz);
+  const unsigned cm = (unsigned)wrapi((int)col - 1, nz), cp = (unsigned)wrapi((int)col + 1, nz);
   const bool out_lane = lane >= 6 && lane < 6 + wi.ncols;
-  const R* __restrict__ fin = g.fin + I.base;
+  const Planes<R> pin = make_planes<R>(g.fin + I.base, g.plane);
   R* __restrict__ fout = g.fout + I.base;
   const long long P = g.plane;
+  const unsigned bcol = col * (unsigned)sizeof(R), bm = cm * (unsigned)sizeof(R), bp = cp * (unsigned)sizeof(R);
   const int s = wi.s, e = wi.e;
   const int a_lo = max(0, s - 6), a_hi = min(nr, e + 6);
   const int b_lo = max(0, s - 4), b_hi = min(nr, e + 4);
@@ -219,7 +304,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
       const int x = t;
       if (x >= a_lo && x < a_hi) {
         R f[9];
-        gather<R>(fin, P, nz, nr, I.bc_top, x, cm, col, cp, f);
+        gather_b<R>(pin, nz, nr, I.bc_top, x, bm, bcol, bp, f);
         const R sg = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
         const R jz = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
         const R jr = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
@@ -289,16 +374,17 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
           const R drr = stencil_dr<R, W>(Vdr, m2, m1, s0, p1, p2);
           const R drz = stencil_dr<R, W>(Vdz, m2, m1, s0, p1, p2);
           const R psi = psi_ref + Vpsi(s0, 0), dz = Vdz(s0, 0), dr = Vdr(s0, 0);
-          const R r = R(x) + R(0.5);
+          const R ir = R(g.inv_r[x]);  // 1/r_j, uniform: a scalar load
           const R K = I.faxis_sound ? R(1.0 / 9.0) : kap * kap;
-          const R gz_ = drz / r;
-          const R gr_ = drr / r - dr / (r * r);
-          fz += R(3) * K * (psi * gz_ + R(6) * A / r * dr * dz);
-          fr += R(3) * K * (psi * gr_ + R(6) * A / r * dr * dr);
+          const R gz_ = drz * ir;
+          const R gr_ = drr * ir - dr * (ir * ir);
+          fz += R(3) * K * (psi * gz_ + R(6) * A * ir * dr * dz);
+          fr += R(3) * K * (psi * gr_ + R(6) * A * ir * dr * dr);
         }
         fz += gzf;
-        const R uz = (jz + R(0.5) * fz) / rho;
-        const R ur = (jr + R(0.5) * fr) / rho;
+        const R irho = recip(rho);
+        const R uz = (jz + R(0.5) * fz) * irho;
+        const R ur = (jr + R(0.5) * fr) * irho;
         fc0z = fz;
         fc0r = fr;
         ring[R_UZ][s0][l2] = uz;
@@ -325,7 +411,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
       if (x >= s && x < e) {
         const int m2 = slot(x - 2), m1 = slot(x - 1), s0 = slot(x), p1 = slot(x + 1), p2 = slot(x + 2);
         R f[9];
-        gather<R>(fin, P, nz, nr, I.bc_top, x, cm, col, cp, f);
+        gather_b<R>(pin, nz, nr, I.bc_top, x, bm, bcol, bp, f);
         const R sg = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
         const R jz = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
         const R jr = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
@@ -339,12 +425,12 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
           const R druz = stencil_dr<R, W>(Vuz, m2, m1, s0, p1, p2);
           const R dzur = stencil_dz<R, W>(Vur, m2, m1, s0, p1, p2);
           const R drur = stencil_dr<R, W>(Vur, m2, m1, s0, p1, p2);
-          const R r = R(x) + R(0.5);
+          const R ir = R(g.inv_r[x]);
           const R mu = rho * nu;
           // eq. (axihz); H_r carries -u_r/r so that sum_i c_ir h_i supplies C_r = 2 mu d/dr(u_r/r)
-          const R Hz = (mu * (druz + dzur) - rho * ur * uz) / r;
-          const R Hr = (R(2) * mu * (drur - ur / r) - rho * ur * ur) / r;
-          const R m0 = -rho * ur / r;
+          const R Hz = (mu * (druz + dzur) - rho * ur * uz) * ir;
+          const R Hr = (R(2) * mu * (drur - ur * ir) - rho * ur * ur) * ir;
+          const R m0 = -rho * ur * ir;
           const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
           const R hz3 = R(3) * Hz, hr3 = R(3) * Hr;
           h[0] = w0 * m0;
@@ -357,12 +443,13 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
           h[7] = w2 * (m0 + (-hz3 - hr3));
           h[8] = w2 * (m0 + (hz3 - hr3));
         }
-        const R ubz = jz / rho, ubr = jr / rho;
+        const R irho = recip(rho);
+        const R ubz = jz * irho, ubr = jr * irho;
         R e0[9], de[9];
         // E_i(rho, u_b) - w_i rho_ref, and the exact-difference increment
         // E_i(rho, u_b + F/rho) - E_i(rho, u_b), both in difference form
         shifted_equilibrium<R>(rho, sg, ubz, ubr, e0);
-        edm_increment<R>(rho, ubz, ubr, Fz / rho, Fr / rho, de);
+        edm_increment<R>(rho, ubz, ubr, Fz * irho, Fr * irho, de);
         if (out_lane) {
           R* o = fout + (long long)x * nz + col;
 #pragma unroll
@@ -398,7 +485,7 @@ __global__ void __launch_bounds__(W) k_sweep(SweepArgs<R> g) {
   for (;;) {
     if (lane == 0) s_ticket = atomicAdd(&g.queue[0], 1);
     __syncthreads();
-    const int item = s_ticket;
+    const int item = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform across the workgroup
     __syncthreads();
     if (item >= g.n_items) break;
     run_item<R, W, MOMENTS>(g, g.items[item], ring, lane);
@@ -474,7 +561,7 @@ __global__ void k_export(const R* __restrict__ fin, long long P, int nz, int nr,
        id += (long long)gridDim.x * blockDim.x) {
     const int k = (int)(id % nz), j = (int)(id / nz);
     R f[9];
-    gather<R>(fin, P, nz, nr, bc_top, j, wrapi(k - 1, nz), k, wrapi(k + 1, nz), f);
+    gather<R>(fin, P, nz, nr, bc_top, j, (unsigned)wrapi(k - 1, nz), (unsigned)k, (unsigned)wrapi(k + 1, nz), f);
     for (int i = 0; i < 9; ++i) out[i * n + id] = (double)f[i] + wgt[i] * rho_ref;
   }
 }
@@ -518,7 +605,7 @@ __global__ void __launch_bounds__(256) k_rows(const R* __restrict__ fin, long lo
   const double rj = j + 0.5;
   for (int k = threadIdx.x; k < nz; k += 256) {
     R o[9];
-    gather<R>(f, P, nz, I.nr, I.bc_top, j, wrapi(k - 1, nz), k, wrapi(k + 1, nz), o);
+    gather<R>(f, P, nz, I.nr, I.bc_top, j, (unsigned)wrapi(k - 1, nz), (unsigned)k, (unsigned)wrapi(k + 1, nz), o);
     const R sg = o[0] + o[1] + o[2] + o[3] + o[4] + o[5] + o[6] + o[7] + o[8];
     const double rho = I.rho_ref + (double)sg;
     if (K == 1) {
