@@ -147,6 +147,8 @@ def main():
     ap.add_argument("--graph-chunk", type=int, default=100)
     ap.add_argument("--no-tune", action="store_true", help="use the cached or default launch shape")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stream-copy", type=int, default=0, metavar="BYTES",
+                    help="only run the reference copy kernel on BYTES and print its GB/s")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -159,6 +161,12 @@ def main():
         print("bench.py needs a GPU (the HIP library has no CPU path).", file=sys.stderr)
         sys.exit(2)
     from paper_1512_01977_amd import lbm, workloads
+
+    if args.stream_copy:
+        gbps = lbm.lbm_axi_stream_copy(args.stream_copy, max(1, args.steps))
+        print(json.dumps({"stream_copy_bytes": args.stream_copy, "iters": args.steps,
+                          "GBps": gbps}), flush=True)
+        return
 
     prec = {"fp32": lbm.PREC_FP32, "fp64": lbm.PREC_FP64}
     default_prec = {"batch": "fp32", "large": "fp32", "wave": "fp32", "mode2": "fp32",

@@ -77,11 +77,12 @@ typedef struct {
 
 /* Launch shape of the fused step kernel (chosen by lbm_axi_autotune or set by hand). */
 typedef struct {
-  int32_t width;        /* lanes per workgroup along z: 64, 128, 256 or 512 (12 are halo) */
+  int32_t width;        /* lanes per workgroup along z: 64, 128 or 256 (12 are halo) */
   int32_t seg_rows;     /* rows of r per work item (>= 8), 0 = whole column */
   int32_t persistent;   /* 1: persistent grid draining a work queue; 0: one workgroup per item */
   int32_t grid;         /* persistent grid size, 0 = automatic */
   int32_t xcd_swizzle;  /* 1: neighbouring work items go to the same XCD */
+  int32_t regf;         /* 1: carry gathered populations in registers (no second gather) */
 } lbm_axi_launch;
 
 typedef struct lbm_axi_s* lbm_axi_t;
@@ -172,6 +173,12 @@ lbm_status lbm_axi_set_launch(lbm_axi_t h, const lbm_axi_launch* cfg);
  * restored on the device), keep the fastest, return it and its ms per step. */
 lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch* best,
                             double* best_ms_per_step);
+
+/* Measurement reference, not part of the method: copy `bytes` (a multiple of 16) between
+ * two device buffers the call allocates, `iters` times on the null stream, and return the
+ * read+write rate in GB/s.  Gives the practical HBM copy ceiling and a kernel of known
+ * traffic for calibrating profiler byte counters.  Synchronising. */
+lbm_status lbm_axi_stream_copy(int64_t bytes, int32_t iters, double* gbps);
 
 /* Sizes: number of instances, total nodes, and bytes of one distribution buffer. */
 lbm_status lbm_axi_sizes(lbm_axi_t h, int32_t* n, int64_t* nodes, int64_t* f_bytes);

@@ -138,6 +138,7 @@ lbm_axi_launch default_launch(const lbm_axi_s* h) {
   c.persistent = h->n > 1 ? 1 : 0;
   c.grid = 0;
   c.xcd_swizzle = 1;
+  c.regf = 0;
   return c;
 }
 
@@ -195,7 +196,7 @@ void drop_graph(lbm_axi_s* h) {
 lbm_status apply_launch(lbm_axi_s* h, const lbm_axi_launch& c) {
   if (!valid_width(c.width)) return LBM_ERR_UNSUPPORTED;
   if (c.seg_rows != 0 && c.seg_rows < 8) return LBM_ERR_ARG;
-  if (c.grid < 0) return LBM_ERR_ARG;
+  if (c.grid < 0 || (c.regf != 0 && c.regf != 1)) return LBM_ERR_ARG;
   lbm_status s = upload_items(h, build_items(h, c, -1));
   if (s != LBM_OK) return s;
   h->launch = c;
@@ -228,7 +229,7 @@ hipError_t enqueue_sweep(lbm_axi_s* h, bool moments, int inst_for_moments, doubl
   g.inv_r = h->d_inv_r;
   (void)inst_for_moments;
   return sweep_dispatch<R>(g, h->launch.width, moments, moments ? false : h->launch.persistent != 0,
-                           moments ? h->n_items : grid_of(h), h->stream);
+                           moments ? false : h->launch.regf != 0, moments ? h->n_items : grid_of(h), h->stream);
 }
 
 lbm_status enqueue_steps_eager(lbm_axi_s* h, int64_t nsteps) {
@@ -474,7 +475,7 @@ hipError_t enqueue_moments(lbm_axi_s* h, int k, double* mr, double* mz, double* 
   g.mur = mu;
   g.inv_r = h->d_inv_r;
   (void)k;
-  return sweep_dispatch<R>(g, h->launch.width, true, false, h->n_items, h->stream);
+  return sweep_dispatch<R>(g, h->launch.width, true, false, false, h->n_items, h->stream);
 }
 
 }  // namespace
@@ -617,7 +618,7 @@ lbm_status lbm_axi_moments(lbm_axi_t h, int32_t k, double* rho, double* uz, doub
   HIPCHK(hipMalloc(&tmp, 3 * n * sizeof(double)));
   // moments of instance k: a work list restricted to it
   const int saved_items = h->n_items;
-  std::vector<WorkItem> items = build_items(h, lbm_axi_launch{h->launch.width, h->launch.seg_rows, 0, 0, 0}, k);
+  std::vector<WorkItem> items = build_items(h, lbm_axi_launch{h->launch.width, h->launch.seg_rows, 0, 0, 0, 0}, k);
   WorkItem* d_items = nullptr;
   lbm_status st = LBM_OK;
   if (hipMalloc(&d_items, items.size() * sizeof(WorkItem)) != hipSuccess) st = LBM_ERR_ALLOC;
@@ -730,6 +731,38 @@ lbm_status lbm_axi_sizes(lbm_axi_t h, int32_t* n, int64_t* nodes, int64_t* f_byt
   return LBM_OK;
 }
 
+lbm_status lbm_axi_stream_copy(int64_t bytes, int32_t iters, double* gbps) {
+  if (bytes < 16 || (bytes & 15) || iters < 1 || !gbps) return LBM_ERR_ARG;
+  void *a = nullptr, *b = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  lbm_status st = LBM_OK;
+  int dev = 0, cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    cus = prop.multiProcessorCount;
+  if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) st = LBM_ERR_ALLOC;
+  if (st == LBM_OK && (hipMemset(a, 0, bytes) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+                       hipEventCreate(&e1) != hipSuccess))
+    st = LBM_ERR_HIP;
+  const int grid = cus * 32;
+  if (st == LBM_OK && launch_copy(a, b, bytes, grid, nullptr) != hipSuccess) st = LBM_ERR_HIP;  // warm-up
+  if (st == LBM_OK) {
+    (void)hipEventRecord(e0, nullptr);
+    for (int i = 0; i < iters && st == LBM_OK; ++i)
+      if (launch_copy(a, b, bytes, grid, nullptr) != hipSuccess) st = LBM_ERR_HIP;
+    (void)hipEventRecord(e1, nullptr);
+    float ms = 0.f;
+    if (st == LBM_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = LBM_ERR_HIP;
+    if (st == LBM_OK) *gbps = 2.0 * (double)bytes * iters / (ms * 1e-3) / 1e9;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (a) (void)hipFree(a);
+  if (b) (void)hipFree(b);
+  return st;
+}
+
 lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch* best, double* best_ms) {
   if (!h || steps_per_trial < 1) return LBM_ERR_ARG;
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -752,8 +785,9 @@ lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch
     if (st != LBM_OK) break;
     if (w > 64 && maxnz + 12 <= w / 2) continue;  // most lanes would duplicate columns
     for (int sg : segs)
-      for (int pers = 0; pers <= 1 && st == LBM_OK; ++pers) {
-        lbm_axi_launch c{w, sg, pers, 0, 1};
+      for (int v = 0; v < 4 && st == LBM_OK; ++v) {
+        const int pers = v & 1, regf = v >> 1;
+        lbm_axi_launch c{w, sg, pers, 0, 1, regf};
         if (apply_launch(h, c) != LBM_OK) continue;
         if (enqueue_steps_eager(h, 1) != LBM_OK) {  // warm-up
           st = LBM_ERR_HIP;

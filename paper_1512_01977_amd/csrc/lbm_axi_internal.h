@@ -56,8 +56,8 @@ struct RowRef {
 };
 
 template <typename R>
-hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool persist, int grid,
-                          hipStream_t st);
+hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool persist, bool regf,
+                          int grid, hipStream_t st);
 template <typename R>
 hipError_t launch_unstream(R* fout, long long P, int nz, int nr, int bc_top, double rho_ref,
                            const double* rho0,
@@ -68,6 +68,7 @@ hipError_t launch_export(const R* fin, long long P, int nz, int nr, int bc_top, 
 template <typename R>
 hipError_t launch_rows(int K, const R* fin, long long P, const InstDev* inst, const RowRef* rows,
                        int nrows, const double* geo, double* part, hipStream_t st);
+hipError_t launch_copy(const void* src, void* dst, long long bytes, int grid, hipStream_t st);
 hipError_t launch_finish(int K, const double* part, const int* row_start, const InstDev* inst, int n,
                          double* out, hipStream_t st);
 

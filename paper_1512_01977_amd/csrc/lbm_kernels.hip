@@ -256,7 +256,9 @@ __device__ __forceinline__ R stencil_dr(const RingView<R, W>& v, int m2, int m1,
   return s * R(1.0 / 36.0);
 }
 
-template <typename R, int W, bool MOMENTS>
+// REGF: carry the populations gathered in stage A for six rows in registers instead of
+// gathering them again in stage D (fewer loads that miss L2, more registers).
+template <typename R, int W, bool MOMENTS, bool REGF>
 __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem wi, R (*ring)[RD][W + 4],
                                          int lane) {
   const InstDev I = g.inst[wi.inst];
@@ -287,7 +289,19 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
   R fc0z = 0, fc0r = 0, fc1z = 0, fc1r = 0, fc2z = 0, fc2r = 0;
   int bad = 0;
 
+  R fd[REGF ? 7 : 1][9];  // populations of rows t .. t-6 (REGF only)
+#pragma unroll
+  for (int a = 0; a < (REGF ? 7 : 1); ++a)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fd[a][i] = R(0);
+
   for (int t = a_lo; t < e + 6; ++t) {
+    if (REGF) {
+#pragma unroll
+      for (int a = 6; a > 0; --a)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fd[REGF ? a : 0][i] = fd[REGF ? a - 1 : 0][i];
+    }
 #pragma unroll
     for (int q = 4; q > 0; --q) {
       rho_d[q] = rho_d[q - 1];
@@ -319,6 +333,10 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         ring[R_PSI][slot(x)][l2] = psi;
         if (x == 0) ring[R_PSI][slot(-1)][l2] = psi;  // psi is even across the axis
         if (x == 1) ring[R_PSI][slot(-2)][l2] = psi;
+        if (REGF) {
+#pragma unroll
+          for (int i = 0; i < 9; ++i) fd[0][i] = f[i];
+        }
         rho_d[0] = rho;
         sg_d[0] = sg;
         jz_d[0] = jz;
@@ -411,7 +429,12 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
       if (x >= s && x < e) {
         const int m2 = slot(x - 2), m1 = slot(x - 1), s0 = slot(x), p1 = slot(x + 1), p2 = slot(x + 2);
         R f[9];
-        gather_b<R>(pin, nz, nr, I.bc_top, x, bm, bcol, bp, f);
+        if (REGF) {
+#pragma unroll
+          for (int i = 0; i < 9; ++i) f[i] = fd[REGF ? 6 : 0][i];
+        } else {
+          gather_b<R>(pin, nz, nr, I.bc_top, x, bm, bcol, bp, f);
+        }
         const R sg = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
         const R jz = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
         const R jr = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
@@ -471,7 +494,7 @@ __device__ __forceinline__ int xcd_map(int b, int G) {
   return xcd < rem ? xcd * (q + 1) + pos : rem * (q + 1) + (xcd - rem) * q + pos;
 }
 
-template <typename R, int W, bool MOMENTS, bool PERSIST>
+template <typename R, int W, bool MOMENTS, bool PERSIST, bool REGF>
 __global__ void __launch_bounds__(W) k_sweep(SweepArgs<R> g) {
   __shared__ R ring[NRING][RD][W + 4];
   __shared__ int s_ticket;
@@ -479,7 +502,7 @@ __global__ void __launch_bounds__(W) k_sweep(SweepArgs<R> g) {
   if (!PERSIST) {
     const int b = (int)blockIdx.x;
     const int item = g.xcd_swizzle ? xcd_map(b, (int)gridDim.x) : b;
-    if (item < g.n_items) run_item<R, W, MOMENTS>(g, g.items[item], ring, lane);
+    if (item < g.n_items) run_item<R, W, MOMENTS, REGF>(g, g.items[item], ring, lane);
     return;
   }
   for (;;) {
@@ -488,7 +511,7 @@ __global__ void __launch_bounds__(W) k_sweep(SweepArgs<R> g) {
     const int item = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform across the workgroup
     __syncthreads();
     if (item >= g.n_items) break;
-    run_item<R, W, MOMENTS>(g, g.items[item], ring, lane);
+    run_item<R, W, MOMENTS, REGF>(g, g.items[item], ring, lane);
   }
   if (lane == 0) {
     // The last workgroup out rewinds the queue for the next launch (no memset needed,
@@ -659,22 +682,42 @@ __global__ void __launch_bounds__(256) k_finish(const double* __restrict__ part,
   (void)inst;
 }
 
+// ---------------------------------------------------------------------------- copy (bandwidth reference)
+
+// Plain streaming copy, 16 bytes per lane per access, grid-stride.  Used to measure the
+// practical HBM copy rate and to calibrate the byte counters of the profiler.
+__global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ src, float4* __restrict__ dst,
+                                              long long n16) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n16;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+hipError_t launch_copy(const void* src, void* dst, long long bytes, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, st, static_cast<const float4*>(src),
+                     static_cast<float4*>(dst), bytes / 16);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------- host-side launchers
 
-template <typename R, int W, bool MOMENTS, bool PERSIST>
+template <typename R, int W, bool MOMENTS, bool PERSIST, bool REGF>
 static hipError_t launch_sweep(const SweepArgs<R>& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_sweep<R, W, MOMENTS, PERSIST>), dim3(grid), dim3(W), 0, st, g);
+  hipLaunchKernelGGL((k_sweep<R, W, MOMENTS, PERSIST, REGF>), dim3(grid), dim3(W), 0, st, g);
   return hipGetLastError();
 }
 
 template <typename R>
-hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool persist, int grid,
+hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool persist, bool regf, int grid,
                           hipStream_t st) {
-#define LBM_CASE(WW)                                                          \
-  case WW:                                                                    \
-    if (moments) return launch_sweep<R, WW, true, false>(g, grid, st);        \
-    if (persist) return launch_sweep<R, WW, false, true>(g, grid, st);        \
-    return launch_sweep<R, WW, false, false>(g, grid, st);
+#define LBM_CASE(WW)                                                                        \
+  case WW:                                                                                  \
+    if (moments) return launch_sweep<R, WW, true, false, false>(g, grid, st);               \
+    if (persist)                                                                            \
+      return regf ? launch_sweep<R, WW, false, true, true>(g, grid, st)                     \
+                  : launch_sweep<R, WW, false, true, false>(g, grid, st);                   \
+    return regf ? launch_sweep<R, WW, false, false, true>(g, grid, st)                      \
+                : launch_sweep<R, WW, false, false, false>(g, grid, st);
   switch (width) {
     LBM_CASE(64)
     LBM_CASE(128)
@@ -686,8 +729,8 @@ hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool p
   return hipErrorInvalidValue;
 }
 
-template hipError_t sweep_dispatch<float>(const SweepArgs<float>&, int, bool, bool, int, hipStream_t);
-template hipError_t sweep_dispatch<double>(const SweepArgs<double>&, int, bool, bool, int, hipStream_t);
+template hipError_t sweep_dispatch<float>(const SweepArgs<float>&, int, bool, bool, bool, int, hipStream_t);
+template hipError_t sweep_dispatch<double>(const SweepArgs<double>&, int, bool, bool, bool, int, hipStream_t);
 
 template <typename R>
 hipError_t launch_unstream(R* fout, long long P, int nz, int nr, int bc_top, double rho_ref, const double* rho0,

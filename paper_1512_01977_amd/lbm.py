@@ -33,7 +33,8 @@ EXPORTS = [
     "lbm_axi_step", "lbm_axi_step_timed", "lbm_axi_sync", "lbm_axi_errors",
     "lbm_axi_set_graph_chunk",
     "lbm_axi_moments", "lbm_axi_mass", "lbm_axi_laplace", "lbm_axi_get_f", "lbm_axi_set_f",
-    "lbm_axi_get_launch", "lbm_axi_set_launch", "lbm_axi_autotune", "lbm_axi_sizes",
+    "lbm_axi_get_launch", "lbm_axi_set_launch", "lbm_axi_autotune", "lbm_axi_stream_copy",
+    "lbm_axi_sizes",
 ]
 
 
@@ -62,7 +63,7 @@ class lbm_axi_params(ctypes.Structure):
 class lbm_axi_launch(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("seg_rows", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("xcd_swizzle", ctypes.c_int32)]
+                ("xcd_swizzle", ctypes.c_int32), ("regf", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -137,6 +138,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_axi_get_launch.argtypes = [_H, LP]
         L.lbm_axi_set_launch.argtypes = [_H, LP]
         L.lbm_axi_autotune.argtypes = [_H, ctypes.c_int32, LP, _dp]
+        L.lbm_axi_stream_copy.argtypes = [ctypes.c_int64, ctypes.c_int32, _dp]
         L.lbm_axi_sizes.argtypes = [_H, ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         for name in EXPORTS:
@@ -174,6 +176,13 @@ def lbm_axi_eos_coexistence(p: Params):
     _check(lib().lbm_axi_eos_coexistence(ctypes.byref(p.c()), ctypes.byref(a), ctypes.byref(b),
                                          ctypes.byref(c)), "lbm_axi_eos_coexistence")
     return a.value, b.value, c.value
+
+
+def lbm_axi_stream_copy(nbytes: int, iters: int = 10) -> float:
+    """Device-to-device copy rate in GB/s (read + write) of a plain streaming kernel."""
+    g = ctypes.c_double()
+    _check(lib().lbm_axi_stream_copy(int(nbytes), int(iters), ctypes.byref(g)), "lbm_axi_stream_copy")
+    return g.value
 
 
 def _current_stream():

@@ -64,14 +64,17 @@ def test_static_droplet_1000_steps_fp64():
 
 
 LAUNCHES = [
-    dict(width=64, seg_rows=8, persistent=0, xcd_swizzle=0),
-    dict(width=64, seg_rows=16, persistent=1, xcd_swizzle=1),
-    dict(width=128, seg_rows=0, persistent=0, xcd_swizzle=1),
-    dict(width=256, seg_rows=13, persistent=1, xcd_swizzle=1),
+    dict(width=64, seg_rows=8, persistent=0, xcd_swizzle=0, regf=0),
+    dict(width=64, seg_rows=16, persistent=1, xcd_swizzle=1, regf=1),
+    dict(width=128, seg_rows=0, persistent=0, xcd_swizzle=1, regf=1),
+    dict(width=128, seg_rows=9, persistent=1, xcd_swizzle=0, regf=0),
+    dict(width=256, seg_rows=13, persistent=1, xcd_swizzle=1, regf=0),
+    dict(width=256, seg_rows=20, persistent=0, xcd_swizzle=1, regf=1),
 ]
 
 
-@pytest.mark.parametrize("launch", LAUNCHES, ids=lambda c: f"w{c['width']}s{c['seg_rows']}p{c['persistent']}")
+@pytest.mark.parametrize("launch", LAUNCHES,
+                         ids=lambda c: f"w{c['width']}s{c['seg_rows']}p{c['persistent']}r{c['regf']}")
 def test_launch_shapes_agree_with_oracle(launch):
     # strips with ragged tails (nz = 150 is no multiple of width - 12) and row segments
     d = base(150, 37, A=-0.152, tau=0.9)
