@@ -129,17 +129,45 @@ InstDev make_inst(const lbm_axi_params& p, long long base, double rho_ref) {
 
 bool valid_width(int w) { return w == 64 || w == 128 || w == 256; }
 
+// Work-item count and lane-iterations of a launch shape (cost model of the default shape).
+void shape_cost(const lbm_axi_s* h, int width, int seg, long long* items, long long* lane_iters,
+                int* longest) {
+  *items = 0;
+  *lane_iters = 0;
+  *longest = 0;
+  const int wout = width - 12;
+  for (const auto& p : h->prm) {
+    const int sg = seg > 0 ? std::min(seg, p.nr) : p.nr;
+    const long long nstrip = std::max(1, (p.nz + wout - 1) / wout);
+    const long long nseg = (p.nr + sg - 1) / sg;
+    const int rows = sg + std::min(12, p.nr - sg + 12);  // segment plus its pipeline rows
+    *items += nstrip * nseg;
+    *lane_iters += nstrip * nseg * (long long)width * rows;
+    *longest = std::max(*longest, rows);
+  }
+}
+
+// Default shape without timing anything: minimise max(total lane-iterations / lanes the chip
+// keeps in flight, longest item / 3), the second term being the chain of one work item when
+// the chip is under-filled (its waves then run about three times faster).
 lbm_axi_launch default_launch(const lbm_axi_s* h) {
-  lbm_axi_launch c{};
-  int maxnz = 0;
-  for (auto& p : h->prm) maxnz = std::max(maxnz, p.nz);
-  c.width = maxnz >= 244 ? 256 : (maxnz >= 116 ? 128 : 64);
-  c.seg_rows = 256;
-  c.persistent = h->n > 1 ? 1 : 0;
-  c.grid = 0;
-  c.xcd_swizzle = 1;
-  c.regf = 0;
-  return c;
+  lbm_axi_launch best{};
+  double best_t = 1e300;
+  const double cap = (double)h->cus * 4 * 64 * 3;
+  const int widths[] = {64, 128, 256};
+  const int segs[] = {8, 16, 32, 64, 128, 256, 512, 0};
+  for (int w : widths)
+    for (int sg : segs) {
+      long long items, lane_iters;
+      int longest;
+      shape_cost(h, w, sg, &items, &lane_iters, &longest);
+      const double t = std::max((double)lane_iters / cap, longest / 3.0);
+      if (t < best_t * 0.999) {
+        best_t = t;
+        best = lbm_axi_launch{w, sg, h->n > 1 ? 1 : 0, 0, 1, 0};
+      }
+    }
+  return best;
 }
 
 // Strips of width - 12 output columns times row segments, for every instance.
