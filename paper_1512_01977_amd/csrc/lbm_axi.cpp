@@ -115,11 +115,21 @@ InstDev make_inst(const lbm_axi_params& p, long long base, double rho_ref) {
   d.axisym = p.axisym;
   d.faxis_sound = p.faxis_sound;
   d.bc_top = p.bc_top;
-  d.T = p.T;
-  d.a = p.eos_a;
-  d.b = p.eos_b;
-  d.R = p.eos_R;
-  d.lam = p.lambda;
+  d.psi_ref2 = d.psi_ref * d.psi_ref;
+  if (p.eos == LBM_EOS_CS) {
+    d.c1 = p.lambda * p.eos_R * p.T;
+    d.c2 = p.lambda * p.eos_a;
+    d.ce = 0.25 * p.eos_b;
+    d.rmax = 4.0 / p.eos_b;
+  } else if (p.eos == LBM_EOS_VDW) {
+    d.c1 = 8.0 * p.lambda * p.T;
+    d.c2 = 3.0 * p.lambda;
+    d.ce = 0.0;
+    d.rmax = 3.0;
+  } else {
+    d.c1 = d.c2 = d.ce = 0.0;
+    d.rmax = HUGE_VAL;
+  }
   d.A = p.A;
   d.omega = 1.0 / p.tau;
   d.nu = (p.tau - 0.5) / 3.0;

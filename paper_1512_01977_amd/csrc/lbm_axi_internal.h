@@ -18,13 +18,17 @@ struct InstDev {
   long long base;    // index of node (0, 0) of the instance inside every distribution plane
   int nz, nr;
   int eos, axisym, faxis_sound, bc_top;
-  double T, a, b, R, lam;  // EOS coefficients (FP64 in every precision)
+  // EOS in the form the kernels evaluate (FP64 in every precision):
+  //   Carnahan-Starling  P = c1 rho n(e) / (1 - e)^3 - c2 rho^2, e = ce rho (c1 = lambda R T, c2 = lambda a, ce = b / 4)
+  //   van der Waals      P = c1 rho / (3 - rho) - c2 rho^2       (c1 = 8 lambda T, c2 = 3 lambda)
+  // rmax: the density where the repulsive term diverges (the EOS domain ends there).
+  double c1, c2, ce, rmax;
   double A, omega, nu, gz; // A, 1/tau, (tau - 1/2)/3, body force density
   // Storage shift: the planes hold g_i = f_i - w_i rho_ref and the psi ring holds
   // psi - psi_ref, psi_ref = psi(rho_ref).  In FP32 this keeps the momentum (a small
   // difference of O(rho) populations) and the psi gradients at full relative precision;
   // FP64 uses rho_ref = psi_ref = 0.
-  double rho_ref, psi_ref;
+  double rho_ref, psi_ref, psi_ref2;  // psi_ref2 = psi_ref^2
 };
 
 // One unit of work of the fused step kernel: a strip of output columns

@@ -54,30 +54,31 @@ __device__ __forceinline__ double recip(double x) {
   return __builtin_fma(r, e, r);
 }
 
-// P_k and kappa = dP_k/drho in FP64 (Sec. 2.3; Carnahan-Starling in the same slot).
+// Fused multiply-add in the storage precision (the plain builtin would promote floats).
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// P_k and kappa = dP_k/drho in FP64 (Sec. 2.3; Carnahan-Starling in the same slot), from the
+// per-instance constants c1, c2, ce (see InstDev).
 __device__ __forceinline__ void eos_dev(const InstDev& I, double rho, double& P, double& kap) {
   if (I.eos == LBM_EOS_CS) {
-    const double e = 0.25 * I.b * rho;
+    const double e = I.ce * rho;
     const double im = recip(1.0 - e);
     const double im3 = im * im * im;
     const double num = 1.0 + e * (1.0 + e * (1.0 - e));
     const double dnum = 1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)));
-    P = I.lam * (I.R * I.T * rho * num * im3 - I.a * rho * rho);
-    kap = I.lam * (I.R * I.T * dnum * im3 * im - 2.0 * I.a * rho);
+    const double c2r = I.c2 * rho;
+    P = __builtin_fma(I.c1 * rho * num, im3, -c2r * rho);
+    kap = __builtin_fma(I.c1 * dnum, im3 * im, -2.0 * c2r);
   } else if (I.eos == LBM_EOS_VDW) {
     const double id = recip(3.0 - rho);
-    P = I.lam * (8.0 * rho * I.T * id - 3.0 * rho * rho);
-    kap = I.lam * (24.0 * I.T * id * id - 6.0 * rho);
+    const double c2r = I.c2 * rho;
+    P = __builtin_fma(I.c1 * rho, id, -c2r * rho);
+    kap = __builtin_fma(3.0 * I.c1 * id, id, -2.0 * c2r);
   } else {
-    P = rho / 3.0;
+    P = rho * (1.0 / 3.0);
     kap = 1.0 / 3.0;
   }
-}
-
-__device__ __forceinline__ bool in_domain(const InstDev& I, double rho) {
-  if (I.eos == LBM_EOS_CS) return rho < 4.0 / I.b;
-  if (I.eos == LBM_EOS_VDW) return rho < 3.0;
-  return true;
 }
 
 // Post-streaming populations of node (col, x) pulled from the post-collision
@@ -151,6 +152,19 @@ __device__ __forceinline__ R pload(const Planes<R>& pl, int q, unsigned voff, un
   return bload(R(0), pl.g[q / 3], voff, row_off + (unsigned)(q % 3) * pl.pstride);
 }
 
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+}
+
+template <typename R>
+__device__ __forceinline__ void pstore(const Planes<R>& pl, int q, R v, unsigned voff, unsigned row_off) {
+  bstore(v, pl.g[q / 3], voff, row_off + (unsigned)(q % 3) * pl.pstride);
+}
+
 // bm, b0, bp: byte offsets of columns k-1, k, k+1 within a row.
 template <typename R>
 __device__ __forceinline__ void gather_b(const Planes<R>& pl, int nz, int nr, int bc_top, int x, unsigned bm,
@@ -205,86 +219,141 @@ __device__ __forceinline__ void shifted_equilibrium(R rho, R sg, R uz, R ur, R e
   e[8] = E(w2, uz - ur);
 }
 
-// E_i(rho, u + du) - E_i(rho, u) = w_i rho [3 c.du + 4.5 (c.du)(c.(2u + du)) - 1.5 du.(2u + du)]
-template <typename R>
-__device__ __forceinline__ void edm_increment(R rho, R uz, R ur, R dz, R dr, R d[9]) {
-  const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
-  const R sz = R(2) * uz + dz, sr = R(2) * ur + dr;
-  const R m = R(-1.5) * (dz * sz + dr * sr);
-  auto D = [&](R w, R cd, R cs) { return w * rho * (m + R(3.0) * cd + R(4.5) * cd * cs); };
-  d[0] = w0 * rho * m;
-  d[1] = D(w1, dz, sz);
-  d[2] = D(w1, dr, sr);
-  d[3] = D(w1, -dz, -sz);
-  d[4] = D(w1, -dr, -sr);
-  d[5] = D(w2, dz + dr, sz + sr);
-  d[6] = D(w2, -dz + dr, -sz + sr);
-  d[7] = D(w2, -dz - dr, -sz - sr);
-  d[8] = D(w2, dz - dr, sz - sr);
-}
-
-// Stencil readers over a ring: V(row slot, z offset).
+// LDS rings, interleaved: element (ring q, row slot s, column c) sits at
+// [s][c][q], so the five fields of one column are adjacent and a whole row of
+// stencil reads (columns lane .. lane + 4) lies within 100 bytes of one base.  Every
+// access is one per-lane base plus the uniform slot offset (rb = s * ROWB) plus an
+// immediate; lanes step NRING elements apart, an odd dword stride (no bank conflicts).
 template <typename R, int W>
-struct RingView {
-  R (*ring)[W + 4];  // [RD][W + 4]
-  int l;             // lane + 2
-  __device__ __forceinline__ R operator()(int s, int dz) const { return ring[s][l + dz]; }
+struct Rings {
+  static constexpr int ROWB = (W + 4) * NRING * (int)sizeof(R);
+  char* lane;  // address of slot 0, column lane (the node's dz = -2 neighbour), ring 0
+  __device__ __forceinline__ R& at(int q, int rb, int dz) const {
+    return *reinterpret_cast<R*>(lane + rb + ((2 + dz) * NRING + q) * (int)sizeof(R));
+  }
 };
 
-// D_z g at the row with slots (m2, m1, s0, p1, p2) for rows x-2..x+2, in the direction
-// order 1, 3, 5, 6, 7, 8 of the stencil sum.
+// A ring's five rows x-2 .. x+2 as slot byte offsets.
+struct Rows5 {
+  int m2, m1, s0, p1, p2;
+};
+
+// D_z g (eq. fifthorderaccuratefinitedifference): directions 1, 3, 5, 6, 7, 8, each
+// 8 g(x + c_i) - g(x + 2 c_i) weighted by c_iz; unscaled (the caller multiplies by 1/36).
 template <typename R, int W>
-__device__ __forceinline__ R stencil_dz(const RingView<R, W>& v, int m2, int m1, int s0, int p1, int p2) {
-  R s = R(8) * v(s0, 1) - v(s0, 2);
-  s -= R(8) * v(s0, -1) - v(s0, -2);
-  s += R(8) * v(p1, 1) - v(p2, 2);
-  s -= R(8) * v(p1, -1) - v(p2, -2);
-  s -= R(8) * v(m1, -1) - v(m2, -2);
-  s += R(8) * v(m1, 1) - v(m2, 2);
-  return s * R(1.0 / 36.0);
+__device__ __forceinline__ R stencil_dz36(const Rings<R, W>& L, int q, const Rows5& r) {
+  const R a = (L.at(q, r.s0, 1) - L.at(q, r.s0, -1)) + (L.at(q, r.p1, 1) - L.at(q, r.p1, -1)) +
+              (L.at(q, r.m1, 1) - L.at(q, r.m1, -1));
+  const R b = (L.at(q, r.s0, 2) - L.at(q, r.s0, -2)) + (L.at(q, r.p2, 2) - L.at(q, r.p2, -2)) +
+              (L.at(q, r.m2, 2) - L.at(q, r.m2, -2));
+  return fmad(R(8), a, -b);
 }
 
-// D_r g, directions 2, 4, 5, 6, 7, 8.
+// D_r g: directions 2, 4, 5, 6, 7, 8 weighted by c_ir; unscaled.
 template <typename R, int W>
-__device__ __forceinline__ R stencil_dr(const RingView<R, W>& v, int m2, int m1, int s0, int p1, int p2) {
-  R s = R(8) * v(p1, 0) - v(p2, 0);
-  s -= R(8) * v(m1, 0) - v(m2, 0);
-  s += R(8) * v(p1, 1) - v(p2, 2);
-  s += R(8) * v(p1, -1) - v(p2, -2);
-  s -= R(8) * v(m1, -1) - v(m2, -2);
-  s -= R(8) * v(m1, 1) - v(m2, 2);
-  return s * R(1.0 / 36.0);
+__device__ __forceinline__ R stencil_dr36(const Rings<R, W>& L, int q, const Rows5& r) {
+  const R a = (L.at(q, r.p1, -1) + L.at(q, r.p1, 0) + L.at(q, r.p1, 1)) -
+              (L.at(q, r.m1, -1) + L.at(q, r.m1, 0) + L.at(q, r.m1, 1));
+  const R b = (L.at(q, r.p2, -2) + L.at(q, r.p2, 0) + L.at(q, r.p2, 2)) -
+              (L.at(q, r.m2, -2) + L.at(q, r.m2, 0) + L.at(q, r.m2, 2));
+  return fmad(R(8), a, -b);
+}
+
+// Post-collision populations of one node (eq. lbm with the exact-difference forcing of
+// eq. kupershtokhforcing and the source h_i of eq. axihz), in shifted storage:
+//   f*_i = f_i + omega (E_i(rho, u_b) - f_i) + E_i(rho, u_b + F/rho) - E_i(rho, u_b) + h_i,
+//   E_i(rho, v) = w_i rho (1 + Q_i(v)),  Q_i(v) = 3 c_i.v + 4.5 (c_i.v)^2 - 1.5 v.v,
+//   h_i = w_i (m0 + 3 c_i.H).
+// With g_i = f_i - w_i rho_ref and s = rho - rho_ref this is exactly
+//   g*_i = (1 - omega) g_i + w_i [omega s + m0 + rho ((omega - 1) Q_i(u_b) + Q_i(u_a)) + 3 c_i.H],
+// u_a = u_b + F/rho, and since Q_i is a quadratic form in c_i the bracket is
+//   M + 4.5 rho c_i.T.c_i + c_i.V,   M = omega s + m0 - 1.5 rho tr T,
+//   T = (omega - 1) u_b u_b + u_a u_a,  V = 3 rho ((omega - 1) u_b + u_a) + 3 H.
+// H3 = 3 H; F = (Fz, Fr).
+template <typename R>
+__device__ __forceinline__ void collide(const R g[9], R rho, R sg, R jz, R jr, R Fz, R Fr, R m0, R H3z, R H3r,
+                                        R omega, R out[9]) {
+  const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
+  const R irho = recip(rho);
+  const R ubz = jz * irho, ubr = jr * irho;
+  const R duz = Fz * irho, dur = Fr * irho;
+  const R uaz = ubz + duz, uar = ubr + dur;
+  const R om1 = omega - R(1);
+  const R tz = om1 * ubz, tr = om1 * ubr;
+  const R Tzz = fmad(tz, ubz, uaz * uaz);
+  const R Trr = fmad(tr, ubr, uar * uar);
+  const R Tzr = fmad(tz, ubr, uaz * uar);
+  const R tT = Tzz + Trr;
+  const R M = fmad(R(-1.5) * rho, tT, fmad(omega, sg, m0));
+  const R r45 = R(4.5) * rho;
+  const R Kz = fmad(r45, Tzz, M);
+  const R Kr = fmad(r45, Trr, M);
+  const R Kd = fmad(r45, tT, M);
+  const R x9 = R(9) * rho * Tzr;
+  const R Kdp = Kd + x9, Kdm = Kd - x9;
+  const R r3 = R(3) * rho;
+  const R Vz = fmad(r3, fmad(omega, ubz, duz), H3z);  // (omega - 1) u_b + u_a = omega u_b + du
+  const R Vr = fmad(r3, fmad(omega, ubr, dur), H3r);
+  const R Sp = Vz + Vr, Sm = Vr - Vz;
+  const R omc = R(1) - omega;
+  out[0] = fmad(omc, g[0], w0 * M);
+  out[1] = fmad(omc, g[1], w1 * (Kz + Vz));
+  out[2] = fmad(omc, g[2], w1 * (Kr + Vr));
+  out[3] = fmad(omc, g[3], w1 * (Kz - Vz));
+  out[4] = fmad(omc, g[4], w1 * (Kr - Vr));
+  out[5] = fmad(omc, g[5], w2 * (Kdp + Sp));
+  out[6] = fmad(omc, g[6], w2 * (Kdm + Sm));
+  out[7] = fmad(omc, g[7], w2 * (Kdp - Sp));
+  out[8] = fmad(omc, g[8], w2 * (Kdm - Sm));
+}
+
+// psi - psi_ref from psi^2 (FP64).  FP64 storage: the FP64 square root.  FP32 storage: the
+// quotient (psi^2 - psi_ref^2) / (psi + psi_ref), whose numerator is formed in FP64 and whose
+// denominator needs only FP32 accuracy; the result is as accurate as its FP32 rounding.
+__device__ __forceinline__ double psi_shifted(double psi2, double psi_ref, double psi_ref2, double) {
+  (void)psi_ref2;
+  return __builtin_sqrt(psi2) - psi_ref;
+}
+__device__ __forceinline__ float psi_shifted(double psi2, double psi_ref, double psi_ref2, float) {
+  const float num = (float)(psi2 - psi_ref2);
+  const float den = __builtin_amdgcn_sqrtf((float)psi2) + (float)psi_ref;
+  return num * recip(__builtin_fmaxf(den, 1e-30f));
 }
 
 // REGF: carry the populations gathered in stage A for six rows in registers instead of
 // gathering them again in stage D (fewer loads that miss L2, more registers).
 template <typename R, int W, bool MOMENTS, bool REGF>
-__device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem wi, R (*ring)[RD][W + 4],
-                                         int lane) {
+__device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem wi, char* lds_lane, int lane) {
   const InstDev I = g.inst[wi.inst];
   const int nz = I.nz, nr = I.nr;
   const unsigned col = (unsigned)wrapi(wi.k0 - 6 + lane, nz);
   const unsigned cm = (unsigned)wrapi((int)col - 1, nz), cp = (unsigned)wrapi((int)col + 1, nz);
   const bool out_lane = lane >= 6 && lane < 6 + wi.ncols;
   const Planes<R> pin = make_planes<R>(g.fin + I.base, g.plane);
-  R* __restrict__ fout = g.fout + I.base;
-  const long long P = g.plane;
+  const Planes<R> pout = make_planes<R>(g.fout + I.base, g.plane);
   const unsigned bcol = col * (unsigned)sizeof(R), bm = cm * (unsigned)sizeof(R), bp = cp * (unsigned)sizeof(R);
   const int s = wi.s, e = wi.e;
   const int a_lo = max(0, s - 6), a_hi = min(nr, e + 6);
   const int b_lo = max(0, s - 4), b_hi = min(nr, e + 4);
   const int c_lo = max(0, s - 2), c_hi = min(nr, e + 2);
-  const R A = R(I.A), omega = R(I.omega), nu = R(I.nu), gzf = R(I.gz);
+  const R omega = R(I.omega), nu = R(I.nu), gzf = R(I.gz), rho_ref = R(I.rho_ref);
+  const R A6 = R(6.0 * I.A), B6 = R(6.0 * (1.0 - 2.0 * I.A));
   const R top_uz = I.bc_top == LBM_TOP_NO_SLIP ? R(-1) : R(1);
   const R psi_ref = R(I.psi_ref), pr2 = R(2.0 * I.psi_ref);
-  const int l2 = lane + 2;
-  const RingView<R, W> Vpsi{ring[R_PSI], l2}, Vdz{ring[R_DZ], l2}, Vdr{ring[R_DR], l2};
-  const RingView<R, W> Vuz{ring[R_UZ], l2}, Vur{ring[R_UR], l2};
+  const Rings<R, W> L{lds_lane};
+  constexpr int ROWB = Rings<R, W>::ROWB;
+  constexpr R i36 = R(1.0 / 36.0);
+
+  // rb[k] = byte offset of the ring slot holding row t - k (slot = row mod 5); stepping t
+  // rotates the five offsets by one.
+  int rb[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) rb[k] = slot(a_lo - k) * ROWB;
 
   // node values travelling from stage A to stage C (ages 0..4) and from B/C onward
-  R rho_d[5], sg_d[5], jz_d[5], jr_d[5], kap_d[5];
+  R rho_d[5], jz_d[5], jr_d[5], kap_d[5];
 #pragma unroll
-  for (int q = 0; q < 5; ++q) rho_d[q] = sg_d[q] = jz_d[q] = jr_d[q] = kap_d[q] = R(0);
+  for (int q = 0; q < 5; ++q) rho_d[q] = jz_d[q] = jr_d[q] = kap_d[q] = R(0);
   R fk0z = 0, fk0r = 0, fk1z = 0, fk1r = 0, fk2z = 0, fk2r = 0;
   R fc0z = 0, fc0r = 0, fc1z = 0, fc1r = 0, fc2z = 0, fc2r = 0;
   int bad = 0;
@@ -305,7 +374,6 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
 #pragma unroll
     for (int q = 4; q > 0; --q) {
       rho_d[q] = rho_d[q - 1];
-      sg_d[q] = sg_d[q - 1];
       jz_d[q] = jz_d[q - 1];
       jr_d[q] = jr_d[q - 1];
       kap_d[q] = kap_d[q - 1];
@@ -313,7 +381,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
     fk2z = fk1z; fk2r = fk1r; fk1z = fk0z; fk1r = fk0r;
     fc2z = fc1z; fc2r = fc1r; fc1z = fc0z; fc1r = fc0r;
 
-    // ------------------------------------------------------------------ A: row t
+    // ------------------------------------------------------------------ A: row t (slot rb[0])
     {
       const int x = t;
       if (x >= a_lo && x < a_hi) {
@@ -323,111 +391,116 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         const R jz = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
         const R jr = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
         const double rd = I.rho_ref + (double)sg;  // rho in FP64 for the EOS
-        const R rho = R(rd);
         double Pk, kap;
         eos_dev(I, rd, Pk, kap);
-        double psi2 = I.eos == LBM_EOS_IDEAL ? 0.0 : rd / 3.0 - Pk;
-        if (!(rd > 0.0) || !in_domain(I, rd) || !(psi2 >= 0.0)) bad |= ERR_BIT_DOMAIN;
-        if (!isfinite(rd) || !isfinite(jz) || !isfinite(jr)) bad |= ERR_BIT_NONFINITE;
-        const R psi = R(sqrt(fmax(psi2, 0.0)) - I.psi_ref);  // stored relative to psi_ref
-        ring[R_PSI][slot(x)][l2] = psi;
-        if (x == 0) ring[R_PSI][slot(-1)][l2] = psi;  // psi is even across the axis
-        if (x == 1) ring[R_PSI][slot(-2)][l2] = psi;
+        const double psi2 = I.eos == LBM_EOS_IDEAL ? 0.0 : fmad(rd, 1.0 / 3.0, -Pk);
+        if (!(rd > 0.0) || !(rd < I.rmax) || !(psi2 >= 0.0)) bad |= ERR_BIT_DOMAIN;
+        if (!isfinite(rd)) bad |= ERR_BIT_NONFINITE;  // any non-finite population makes the sum so
+        const R psi = psi_shifted(__builtin_fmax(psi2, 0.0), I.psi_ref, I.psi_ref2, R(0));
+        L.at(R_PSI, rb[0], 0) = psi;
+        if (x == 0) L.at(R_PSI, rb[1], 0) = psi;  // psi is even across the axis: row -1 = row t - 1
+        if (x == 1) L.at(R_PSI, rb[3], 0) = psi;  // row -2 = row t - 3
         if (REGF) {
 #pragma unroll
           for (int i = 0; i < 9; ++i) fd[0][i] = f[i];
         }
-        rho_d[0] = rho;
-        sg_d[0] = sg;
+        rho_d[0] = R(rd);
         jz_d[0] = jz;
         jr_d[0] = jr;
         kap_d[0] = R(kap);
-      } else if (a_hi == nr && (x == nr || x == nr + 1)) {
-        ring[R_PSI][slot(x)][l2] = ring[R_PSI][slot(2 * nr - 1 - x)][l2];  // even at the wall
+      } else if (a_hi == nr && x == nr) {
+        L.at(R_PSI, rb[0], 0) = L.at(R_PSI, rb[1], 0);  // even at the wall: row nr = row nr - 1
+      } else if (a_hi == nr && x == nr + 1) {
+        L.at(R_PSI, rb[0], 0) = L.at(R_PSI, rb[3], 0);  // row nr + 1 = row nr - 2
       }
     }
     __syncthreads();
 
-    // ------------------------------------------------------------------ B: row t-2
+    // ------------------------------------------------------------------ B: row t-2 (rows t-4 .. t)
     {
       const int x = t - 2;
       if (x >= b_lo && x < b_hi) {
-        const int m2 = slot(x - 2), m1 = slot(x - 1), s0 = slot(x), p1 = slot(x + 1), p2 = slot(x + 2);
-        const R dz = stencil_dz<R, W>(Vpsi, m2, m1, s0, p1, p2);
-        const R dr = stencil_dr<R, W>(Vpsi, m2, m1, s0, p1, p2);
+        const Rows5 r{rb[4], rb[3], rb[2], rb[1], rb[0]};
+        const R dz = stencil_dz36<R, W>(L, R_PSI, r) * i36;
+        const R dr = stencil_dr36<R, W>(L, R_PSI, r) * i36;
         // F_K = 6 [A sum_i w_i psi_i^2 c_i + (1 - 2A) psi sum_i w_i psi_i c_i], i = 1, 2, ..., 8
         const R w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
-        const R q1 = Vpsi(s0, 1), q2 = Vpsi(p1, 0), q3 = Vpsi(s0, -1), q4 = Vpsi(m1, 0);
-        const R q5 = Vpsi(p1, 1), q6 = Vpsi(p1, -1), q7 = Vpsi(m1, -1), q8 = Vpsi(m1, 1);
-        const R s1z = w1 * q1 - w1 * q3 + w2 * q5 - w2 * q6 - w2 * q7 + w2 * q8;
-        const R s1r = w1 * q2 - w1 * q4 + w2 * q5 + w2 * q6 - w2 * q7 - w2 * q8;
+        const R q1 = L.at(R_PSI, r.s0, 1), q2 = L.at(R_PSI, r.p1, 0), q3 = L.at(R_PSI, r.s0, -1);
+        const R q4 = L.at(R_PSI, r.m1, 0), q5 = L.at(R_PSI, r.p1, 1), q6 = L.at(R_PSI, r.p1, -1);
+        const R q7 = L.at(R_PSI, r.m1, -1), q8 = L.at(R_PSI, r.m1, 1);
+        const R s1z = w1 * (q1 - q3) + w2 * ((q5 - q7) + (q8 - q6));
+        const R s1r = w1 * (q2 - q4) + w2 * ((q5 - q7) - (q8 - q6));
         // psi_i^2 = psi_ref^2 + d_i (2 psi_ref + d_i); the constant cancels in sum_i w_i c_i
         const R t1 = q1 * (pr2 + q1), t2 = q2 * (pr2 + q2), t3 = q3 * (pr2 + q3), t4 = q4 * (pr2 + q4);
         const R t5 = q5 * (pr2 + q5), t6 = q6 * (pr2 + q6), t7 = q7 * (pr2 + q7), t8 = q8 * (pr2 + q8);
-        const R s2z = w1 * t1 - w1 * t3 + w2 * t5 - w2 * t6 - w2 * t7 + w2 * t8;
-        const R s2r = w1 * t2 - w1 * t4 + w2 * t5 + w2 * t6 - w2 * t7 - w2 * t8;
-        const R psi = psi_ref + Vpsi(s0, 0);
-        fk0z = R(6) * (A * s2z + (R(1) - R(2) * A) * psi * s1z);
-        fk0r = R(6) * (A * s2r + (R(1) - R(2) * A) * psi * s1r);
-        ring[R_DZ][s0][l2] = dz;
-        ring[R_DR][s0][l2] = dr;
-        if (x == 0) { ring[R_DZ][slot(-1)][l2] = dz; ring[R_DR][slot(-1)][l2] = -dr; }
-        if (x == 1) { ring[R_DZ][slot(-2)][l2] = dz; ring[R_DR][slot(-2)][l2] = -dr; }
-      } else if (b_hi == nr && (x == nr || x == nr + 1)) {
-        const int m = slot(2 * nr - 1 - x), sx = slot(x);
-        ring[R_DZ][sx][l2] = ring[R_DZ][m][l2];   // D_z psi even at the wall
-        ring[R_DR][sx][l2] = -ring[R_DR][m][l2];  // D_r psi odd
+        const R s2z = w1 * (t1 - t3) + w2 * ((t5 - t7) + (t8 - t6));
+        const R s2r = w1 * (t2 - t4) + w2 * ((t5 - t7) - (t8 - t6));
+        const R bpsi = B6 * (psi_ref + L.at(R_PSI, r.s0, 0));
+        fk0z = fmad(A6, s2z, bpsi * s1z);
+        fk0r = fmad(A6, s2r, bpsi * s1r);
+        L.at(R_DZ, r.s0, 0) = dz;
+        L.at(R_DR, r.s0, 0) = dr;
+        if (x == 0) { L.at(R_DZ, rb[3], 0) = dz; L.at(R_DR, rb[3], 0) = -dr; }  // row -1 = row t - 3
+        if (x == 1) { L.at(R_DZ, rb[0], 0) = dz; L.at(R_DR, rb[0], 0) = -dr; }  // row -2 = row t - 5
+      } else if (b_hi == nr && x == nr) {  // D_z psi even, D_r psi odd at the wall
+        L.at(R_DZ, rb[2], 0) = L.at(R_DZ, rb[3], 0);
+        L.at(R_DR, rb[2], 0) = -L.at(R_DR, rb[3], 0);
+      } else if (b_hi == nr && x == nr + 1) {
+        L.at(R_DZ, rb[2], 0) = L.at(R_DZ, rb[0], 0);
+        L.at(R_DR, rb[2], 0) = -L.at(R_DR, rb[0], 0);
       }
     }
     __syncthreads();
 
-    // ------------------------------------------------------------------ C: row t-4
+    // ------------------------------------------------------------------ C: row t-4 (rows t-6 .. t-2)
     {
       const int x = t - 4;
       if (x >= c_lo && x < c_hi) {
-        const int m2 = slot(x - 2), m1 = slot(x - 1), s0 = slot(x), p1 = slot(x + 1), p2 = slot(x + 2);
+        const Rows5 r{rb[1], rb[0], rb[4], rb[3], rb[2]};
         const R rho = rho_d[4], jz = jz_d[4], jr = jr_d[4], kap = kap_d[4];
         R fz = fk2z, fr = fk2r;
         if (I.axisym) {
-          const R drr = stencil_dr<R, W>(Vdr, m2, m1, s0, p1, p2);
-          const R drz = stencil_dr<R, W>(Vdz, m2, m1, s0, p1, p2);
-          const R psi = psi_ref + Vpsi(s0, 0), dz = Vdz(s0, 0), dr = Vdr(s0, 0);
+          // F_axis = 3K/r [psi D_rz psi + 6A D_r psi D_z psi, psi (D_rr psi - D_r psi / r) + 6A (D_r psi)^2]
+          const R drr = stencil_dr36<R, W>(L, R_DR, r) * i36;
+          const R drz = stencil_dr36<R, W>(L, R_DZ, r) * i36;
+          const R psi = psi_ref + L.at(R_PSI, r.s0, 0), dz = L.at(R_DZ, r.s0, 0), dr = L.at(R_DR, r.s0, 0);
           const R ir = R(g.inv_r[x]);  // 1/r_j, uniform: a scalar load
-          const R K = I.faxis_sound ? R(1.0 / 9.0) : kap * kap;
-          const R gz_ = drz * ir;
-          const R gr_ = drr * ir - dr * (ir * ir);
-          fz += R(3) * K * (psi * gz_ + R(6) * A * ir * dr * dz);
-          fr += R(3) * K * (psi * gr_ + R(6) * A * ir * dr * dr);
+          const R k3 = (I.faxis_sound ? R(1.0 / 3.0) : R(3) * kap * kap) * ir;
+          const R a6dr = A6 * dr;
+          fz = fmad(k3, fmad(psi, drz, a6dr * dz), fz);
+          fr = fmad(k3, fmad(psi, fmad(-dr, ir, drr), a6dr * dr), fr);
         }
         fz += gzf;
         const R irho = recip(rho);
-        const R uz = (jz + R(0.5) * fz) * irho;
-        const R ur = (jr + R(0.5) * fr) * irho;
+        const R uz = fmad(R(0.5), fz, jz) * irho;
+        const R ur = fmad(R(0.5), fr, jr) * irho;
         fc0z = fz;
         fc0r = fr;
-        ring[R_UZ][s0][l2] = uz;
-        ring[R_UR][s0][l2] = ur;
-        if (x == 0) { ring[R_UZ][slot(-1)][l2] = uz; ring[R_UR][slot(-1)][l2] = -ur; }
-        if (x == 1) { ring[R_UZ][slot(-2)][l2] = uz; ring[R_UR][slot(-2)][l2] = -ur; }
+        L.at(R_UZ, r.s0, 0) = uz;
+        L.at(R_UR, r.s0, 0) = ur;
+        if (x == 0) { L.at(R_UZ, rb[0], 0) = uz; L.at(R_UR, rb[0], 0) = -ur; }  // row -1 = row t - 5
+        if (x == 1) { L.at(R_UZ, rb[2], 0) = uz; L.at(R_UR, rb[2], 0) = -ur; }  // row -2 = row t - 7
         if (MOMENTS && out_lane && x >= s && x < e) {
           const long long o = (long long)x * nz + col;
           g.mrho[o] = (double)rho;
           g.muz[o] = (double)uz;
           g.mur[o] = (double)ur;
         }
-      } else if (c_hi == nr && (x == nr || x == nr + 1)) {
-        const int m = slot(2 * nr - 1 - x), sx = slot(x);
-        ring[R_UZ][sx][l2] = top_uz * ring[R_UZ][m][l2];
-        ring[R_UR][sx][l2] = -ring[R_UR][m][l2];
+      } else if (c_hi == nr && x == nr) {  // u_r odd; u_z even (free slip) or odd (no slip)
+        L.at(R_UZ, rb[4], 0) = top_uz * L.at(R_UZ, rb[0], 0);
+        L.at(R_UR, rb[4], 0) = -L.at(R_UR, rb[0], 0);
+      } else if (c_hi == nr && x == nr + 1) {
+        L.at(R_UZ, rb[4], 0) = top_uz * L.at(R_UZ, rb[2], 0);
+        L.at(R_UR, rb[4], 0) = -L.at(R_UR, rb[2], 0);
       }
     }
     __syncthreads();
 
-    // ------------------------------------------------------------------ D: row t-6
+    // ------------------------------------------------------------------ D: row t-6 (rows t-8 .. t-4)
     if (!MOMENTS) {
       const int x = t - 6;
       if (x >= s && x < e) {
-        const int m2 = slot(x - 2), m1 = slot(x - 1), s0 = slot(x), p1 = slot(x + 1), p2 = slot(x + 2);
+        const Rows5 r{rb[3], rb[2], rb[1], rb[0], rb[4]};
         R f[9];
         if (REGF) {
 #pragma unroll
@@ -438,47 +511,38 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         const R sg = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
         const R jz = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
         const R jr = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-        const R rho = R(I.rho_ref + (double)sg);
-        const R Fz = fc2z, Fr = fc2r;
-        R h[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) h[i] = R(0);
+        const R rho = rho_ref + sg;
+        R m0 = R(0), H3z = R(0), H3r = R(0);
         if (I.axisym) {
-          const R uz = Vuz(s0, 0), ur = Vur(s0, 0);
-          const R druz = stencil_dr<R, W>(Vuz, m2, m1, s0, p1, p2);
-          const R dzur = stencil_dz<R, W>(Vur, m2, m1, s0, p1, p2);
-          const R drur = stencil_dr<R, W>(Vur, m2, m1, s0, p1, p2);
-          const R ir = R(g.inv_r[x]);
-          const R mu = rho * nu;
           // eq. (axihz); H_r carries -u_r/r so that sum_i c_ir h_i supplies C_r = 2 mu d/dr(u_r/r)
-          const R Hz = (mu * (druz + dzur) - rho * ur * uz) * ir;
-          const R Hr = (R(2) * mu * (drur - ur * ir) - rho * ur * ur) * ir;
-          const R m0 = -rho * ur * ir;
-          const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
-          const R hz3 = R(3) * Hz, hr3 = R(3) * Hr;
-          h[0] = w0 * m0;
-          h[1] = w1 * (m0 + hz3);
-          h[2] = w1 * (m0 + hr3);
-          h[3] = w1 * (m0 - hz3);
-          h[4] = w1 * (m0 - hr3);
-          h[5] = w2 * (m0 + (hz3 + hr3));
-          h[6] = w2 * (m0 + (-hz3 + hr3));
-          h[7] = w2 * (m0 + (-hz3 - hr3));
-          h[8] = w2 * (m0 + (hz3 - hr3));
+          const R uz = L.at(R_UZ, r.s0, 0), ur = L.at(R_UR, r.s0, 0);
+          const R druz = stencil_dr36<R, W>(L, R_UZ, r);  // 36 D_r u_z
+          const R dzur = stencil_dz36<R, W>(L, R_UR, r);  // 36 D_z u_r
+          const R drur = stencil_dr36<R, W>(L, R_UR, r);  // 36 D_r u_r
+          const R ir = R(g.inv_r[x]);
+          const R mu36 = rho * nu * i36;
+          const R ir3 = R(3) * ir;
+          const R rur = rho * ur;
+          H3z = fmad(mu36, druz + dzur, -rur * uz) * ir3;
+          H3r = fmad(R(2) * mu36, fmad(R(-36) * ur, ir, drur), -rur * ur) * ir3;
+          m0 = -rur * ir;
         }
-        const R irho = recip(rho);
-        const R ubz = jz * irho, ubr = jr * irho;
-        R e0[9], de[9];
-        // E_i(rho, u_b) - w_i rho_ref, and the exact-difference increment
-        // E_i(rho, u_b + F/rho) - E_i(rho, u_b), both in difference form
-        shifted_equilibrium<R>(rho, sg, ubz, ubr, e0);
-        edm_increment<R>(rho, ubz, ubr, Fz * irho, Fr * irho, de);
+        R o[9];
+        collide<R>(f, rho, sg, jz, jr, fc2z, fc2r, m0, H3z, H3r, omega, o);
         if (out_lane) {
-          R* o = fout + (long long)x * nz + col;
+          const unsigned orow = (unsigned)x * (unsigned)sizeof(R) * (unsigned)nz;
 #pragma unroll
-          for (int i = 0; i < 9; ++i) o[i * P] = f[i] + omega * (e0[i] - f[i]) + de[i] + h[i];
+          for (int i = 0; i < 9; ++i) pstore(pout, i, o[i], bcol, orow);
         }
       }
+    }
+    {  // row t + 1 takes the slot of row t - 4
+      const int r4 = rb[4];
+      rb[4] = rb[3];
+      rb[3] = rb[2];
+      rb[2] = rb[1];
+      rb[1] = rb[0];
+      rb[0] = r4;
     }
   }
   if (bad) {
@@ -496,13 +560,14 @@ __device__ __forceinline__ int xcd_map(int b, int G) {
 
 template <typename R, int W, bool MOMENTS, bool PERSIST, bool REGF>
 __global__ void __launch_bounds__(W) k_sweep(SweepArgs<R> g) {
-  __shared__ R ring[NRING][RD][W + 4];
+  __shared__ R ring[RD][W + 4][NRING];
   __shared__ int s_ticket;
   const int lane = threadIdx.x;
+  char* const lds_lane = reinterpret_cast<char*>(&ring[0][lane][0]);
   if (!PERSIST) {
     const int b = (int)blockIdx.x;
     const int item = g.xcd_swizzle ? xcd_map(b, (int)gridDim.x) : b;
-    if (item < g.n_items) run_item<R, W, MOMENTS, REGF>(g, g.items[item], ring, lane);
+    if (item < g.n_items) run_item<R, W, MOMENTS, REGF>(g, g.items[item], lds_lane, lane);
     return;
   }
   for (;;) {
@@ -511,7 +576,7 @@ __global__ void __launch_bounds__(W) k_sweep(SweepArgs<R> g) {
     const int item = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform across the workgroup
     __syncthreads();
     if (item >= g.n_items) break;
-    run_item<R, W, MOMENTS, REGF>(g, g.items[item], ring, lane);
+    run_item<R, W, MOMENTS, REGF>(g, g.items[item], lds_lane, lane);
   }
   if (lane == 0) {
     // The last workgroup out rewinds the queue for the next launch (no memset needed,
