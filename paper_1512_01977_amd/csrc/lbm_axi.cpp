@@ -40,7 +40,6 @@ struct lbm_axi_s {
   double* d_part = nullptr;
   double* d_out = nullptr;
   double* d_geo = nullptr;
-  double* d_inv_r = nullptr;
   lbm_axi_launch launch{};
   int cus = 256;
   int graph_chunk = 0;
@@ -264,7 +263,6 @@ hipError_t enqueue_sweep(lbm_axi_s* h, bool moments, int inst_for_moments, doubl
   g.mrho = mr;
   g.muz = mz;
   g.mur = mu;
-  g.inv_r = h->d_inv_r;
   (void)inst_for_moments;
   return sweep_dispatch<R>(g, h->launch.width, moments, moments ? false : h->launch.persistent != 0,
                            moments ? false : h->launch.regf != 0, moments ? h->n_items : grid_of(h), h->stream);
@@ -343,7 +341,7 @@ void free_all(lbm_axi_s* h) {
     if (h->fbuf[0]) (void)hipFree(h->fbuf[0]);
   }
   void* ptrs[] = {h->d_inst, h->d_items, h->d_queue, h->d_err, h->d_rows, h->d_row_start,
-                  h->d_part, h->d_out, h->d_geo, h->d_inv_r};
+                  h->d_part, h->d_out, h->d_geo};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -469,22 +467,16 @@ lbm_status create(int n, const lbm_axi_params* params, int prec, const double* c
   }
   row_start.push_back((int)rows.size());
   h->n_rows = (int)rows.size();
-  int maxnr = 0;
-  for (int k = 0; k < n; ++k) maxnr = std::max(maxnr, params[k].nr);
-  std::vector<double> inv_r(maxnr);
-  for (int j = 0; j < maxnr; ++j) inv_r[j] = 1.0 / (j + 0.5);
   if (hipMalloc(&h->d_inst, n * sizeof(InstDev)) != hipSuccess ||
       hipMalloc(&h->d_queue, 2 * sizeof(int)) != hipSuccess || hipMalloc(&h->d_err, (n + 1) * sizeof(int)) != hipSuccess ||
       hipMalloc(&h->d_rows, rows.size() * sizeof(RowRef)) != hipSuccess ||
       hipMalloc(&h->d_row_start, row_start.size() * sizeof(int)) != hipSuccess ||
       hipMalloc(&h->d_part, rows.size() * 4 * sizeof(double)) != hipSuccess ||
       hipMalloc(&h->d_out, n * sizeof(double)) != hipSuccess ||
-      hipMalloc(&h->d_geo, 3 * n * sizeof(double)) != hipSuccess ||
-      hipMalloc(&h->d_inv_r, maxnr * sizeof(double)) != hipSuccess)
+      hipMalloc(&h->d_geo, 3 * n * sizeof(double)) != hipSuccess)
     return fail(LBM_ERR_ALLOC);
   if (hipMemcpy(h->d_inst, h->hinst.data(), n * sizeof(InstDev), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(h->d_rows, rows.data(), rows.size() * sizeof(RowRef), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(h->d_inv_r, inv_r.data(), maxnr * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(h->d_row_start, row_start.data(), row_start.size() * sizeof(int), hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemset(h->d_queue, 0, 2 * sizeof(int)) != hipSuccess || hipMemset(h->d_err, 0, (n + 1) * sizeof(int)) != hipSuccess)
@@ -511,7 +503,6 @@ hipError_t enqueue_moments(lbm_axi_s* h, int k, double* mr, double* mz, double* 
   g.mrho = mr;
   g.muz = mz;
   g.mur = mu;
-  g.inv_r = h->d_inv_r;
   (void)k;
   return sweep_dispatch<R>(g, h->launch.width, true, false, false, h->n_items, h->stream);
 }

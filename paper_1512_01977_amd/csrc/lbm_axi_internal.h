@@ -49,7 +49,6 @@ struct SweepArgs {
   int xcd_swizzle;
   int* queue;                  // [0] next ticket, [1] finished workgroups (persistent launches)
   int* err;                    // sticky device error bits: [0] any instance, [1 + k] instance k
-  const double* inv_r;         // 1 / (j + 1/2) for every row index j of the tallest instance
   double* mrho;                // moments outputs (moments launches only), instance-local [nr][nz]
   double* muz;
   double* mur;

@@ -39,6 +39,15 @@ __device__ __forceinline__ int slot(int x) {
   return r < 0 ? r + RD : r;
 }
 
+// Workgroup barrier that orders LDS only.  The stages exchange data through LDS alone, so
+// the barrier need not wait for the wave's outstanding global loads and stores (a full
+// __syncthreads() does, which would expose the HBM latency at every pipeline step).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Reciprocals: hardware estimate refined by Newton steps (one for FP32, two for FP64),
 // within an ulp of 1/x; used instead of IEEE division on the hot path.
 __device__ __forceinline__ float recip(float x) {
@@ -165,39 +174,33 @@ __device__ __forceinline__ void pstore(const Planes<R>& pl, int q, R v, unsigned
   bstore(v, pl.g[q / 3], voff, row_off + (unsigned)(q % 3) * pl.pstride);
 }
 
-// bm, b0, bp: byte offsets of columns k-1, k, k+1 within a row.
+// bm, b0, bp: byte offsets of columns k-1, k, k+1 within a row.  The wall cases are
+// chosen with uniform selects of descriptor and offset (and, at a no-slip wall, of the
+// column), so that the nine loads form one straight sequence: the compiler can then
+// track them individually and overlap them with the stores still in flight.
 template <typename R>
 __device__ __forceinline__ void gather_b(const Planes<R>& pl, int nz, int nr, int bc_top, int x, unsigned bm,
                                          unsigned b0, unsigned bp, R o[9]) {
-  const unsigned row = (unsigned)sizeof(R) * (unsigned)nz;
+  const unsigned row = (unsigned)sizeof(R) * (unsigned)nz, ps = pl.pstride;
   const unsigned s0 = (unsigned)x * row;
-  const unsigned sm = x > 0 ? s0 - row : s0;
-  const unsigned sp = x < nr - 1 ? s0 + row : s0;
-  o[0] = pload(pl, 0, b0, s0);
-  o[1] = pload(pl, 1, bm, s0);
-  o[3] = pload(pl, 3, bp, s0);
-  if (x > 0) {
-    o[2] = pload(pl, 2, b0, sm);
-    o[5] = pload(pl, 5, bm, sm);
-    o[6] = pload(pl, 6, bp, sm);
-  } else {
-    o[2] = pload(pl, 4, b0, s0);
-    o[5] = pload(pl, 8, bm, s0);
-    o[6] = pload(pl, 7, bp, s0);
-  }
-  if (x < nr - 1) {
-    o[4] = pload(pl, 4, b0, sp);
-    o[7] = pload(pl, 7, bp, sp);
-    o[8] = pload(pl, 8, bm, sp);
-  } else if (bc_top == LBM_TOP_FREE_SLIP) {
-    o[4] = pload(pl, 2, b0, s0);
-    o[7] = pload(pl, 6, bp, s0);
-    o[8] = pload(pl, 5, bm, s0);
-  } else {
-    o[4] = pload(pl, 2, b0, s0);
-    o[7] = pload(pl, 5, b0, s0);
-    o[8] = pload(pl, 6, b0, s0);
-  }
+  const bool axis = x == 0, top = x == nr - 1;
+  const bool noslip = top && bc_top == LBM_TOP_NO_SLIP;
+  const unsigned sm = s0 - row, sp = s0 + row;
+  // plane q at row offset r: descriptor g[q / 3], scalar offset r + (q % 3) * ps
+  o[0] = bload(R(0), pl.g[0], b0, s0);
+  o[1] = bload(R(0), pl.g[0], bm, s0 + ps);
+  o[3] = bload(R(0), pl.g[1], bp, s0);
+  // c_r = +1 from row x - 1; across the axis (c_z, +1) is (c_z, -1) of node (k - c_z, 0)
+  o[2] = bload(R(0), axis ? pl.g[1] : pl.g[0], b0, axis ? s0 + ps : sm + 2 * ps);       // 4 : 2
+  o[5] = bload(R(0), axis ? pl.g[2] : pl.g[1], bm, axis ? s0 + 2 * ps : sm + 2 * ps);   // 8 : 5
+  o[6] = bload(R(0), pl.g[2], bp, axis ? s0 + ps : sm);                                 // 7 : 6
+  // c_r = -1 from row x + 1; at the wall from (c_z, +1) of node (k - c_z, nr - 1)
+  // (specular) or of the same node with c_z reversed (bounce-back)
+  o[4] = bload(R(0), top ? pl.g[0] : pl.g[1], b0, top ? s0 + 2 * ps : sp + ps);         // 2 : 4
+  o[7] = bload(R(0), top ? (noslip ? pl.g[1] : pl.g[2]) : pl.g[2], noslip ? b0 : bp,
+               top ? (noslip ? s0 + 2 * ps : s0) : sp + ps);                            // 5 | 6 : 7
+  o[8] = bload(R(0), top ? (noslip ? pl.g[2] : pl.g[1]) : pl.g[2], noslip ? b0 : bm,
+               top ? (noslip ? s0 : s0 + 2 * ps) : sp + 2 * ps);                        // 6 | 5 : 8
 }
 
 // Equilibrium of Sec. 2.1 (c_s^2 = 1/3) relative to the storage shift:
@@ -227,13 +230,13 @@ __device__ __forceinline__ void shifted_equilibrium(R rho, R sg, R uz, R ur, R e
 template <typename R, int W>
 struct Rings {
   static constexpr int ROWB = (W + 4) * NRING * (int)sizeof(R);
-  char* lane;  // address of slot 0, column lane (the node's dz = -2 neighbour), ring 0
-  __device__ __forceinline__ R& at(int q, int rb, int dz) const {
-    return *reinterpret_cast<R*>(lane + rb + ((2 + dz) * NRING + q) * (int)sizeof(R));
+  char* base;  // the ring array; rows are addressed by per-lane byte offsets (lane part included)
+  __device__ __forceinline__ R& at(int q, int vb, int dz) const {
+    return *reinterpret_cast<R*>(base + vb + ((2 + dz) * NRING + q) * (int)sizeof(R));
   }
 };
 
-// A ring's five rows x-2 .. x+2 as slot byte offsets.
+// A ring's five rows x-2 .. x+2 as per-lane byte offsets.
 struct Rows5 {
   int m2, m1, s0, p1, p2;
 };
@@ -323,7 +326,7 @@ __device__ __forceinline__ float psi_shifted(double psi2, double psi_ref, double
 // REGF: carry the populations gathered in stage A for six rows in registers instead of
 // gathering them again in stage D (fewer loads that miss L2, more registers).
 template <typename R, int W, bool MOMENTS, bool REGF>
-__device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem wi, char* lds_lane, int lane) {
+__device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem wi, char* lds, int lane) {
   const InstDev I = g.inst[wi.inst];
   const int nz = I.nz, nr = I.nr;
   const unsigned col = (unsigned)wrapi(wi.k0 - 6 + lane, nz);
@@ -340,22 +343,27 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
   const R A6 = R(6.0 * I.A), B6 = R(6.0 * (1.0 - 2.0 * I.A));
   const R top_uz = I.bc_top == LBM_TOP_NO_SLIP ? R(-1) : R(1);
   const R psi_ref = R(I.psi_ref), pr2 = R(2.0 * I.psi_ref);
-  const Rings<R, W> L{lds_lane};
+  const Rings<R, W> L{lds};
   constexpr int ROWB = Rings<R, W>::ROWB;
   constexpr R i36 = R(1.0 / 36.0);
 
-  // rb[k] = byte offset of the ring slot holding row t - k (slot = row mod 5); stepping t
-  // rotates the five offsets by one.
+  // rb[k] = this lane's byte offset in the ring slot holding row t - k (slot = row mod 5);
+  // stepping t rotates the five offsets by one.  They are carried per lane so that each
+  // ring access is a single base register plus an immediate.
   int rb[5];
+  const int lane_off = lane * NRING * (int)sizeof(R);
 #pragma unroll
-  for (int k = 0; k < 5; ++k) rb[k] = slot(a_lo - k) * ROWB;
+  for (int k = 0; k < 5; ++k) rb[k] = lane_off + slot(a_lo - k) * ROWB;
 
-  // node values travelling from stage A to stage C (ages 0..4) and from B/C onward
-  R rho_d[5], jz_d[5], jr_d[5], kap_d[5];
+  // node values travelling from stage A to stage C (age 4) and D (age 6), and from B/C onward
+  R sg_d[7], jz_d[7], jr_d[7], kap_d[5];
 #pragma unroll
-  for (int q = 0; q < 5; ++q) rho_d[q] = jz_d[q] = jr_d[q] = kap_d[q] = R(0);
+  for (int q = 0; q < 7; ++q) sg_d[q] = jz_d[q] = jr_d[q] = R(0);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) kap_d[q] = R(0);
   R fk0z = 0, fk0r = 0, fk1z = 0, fk1r = 0, fk2z = 0, fk2r = 0;
   R fc0z = 0, fc0r = 0, fc1z = 0, fc1r = 0, fc2z = 0, fc2r = 0;
+  R ir0 = 0, ir1 = 0, ir2 = 0;  // 1/r of the stage-C row, two iterations deep
   int bad = 0;
 
   R fd[REGF ? 7 : 1][9];  // populations of rows t .. t-6 (REGF only)
@@ -363,6 +371,10 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
   for (int a = 0; a < (REGF ? 7 : 1); ++a)
 #pragma unroll
     for (int i = 0; i < 9; ++i) fd[a][i] = R(0);
+
+  R fa[9], fg[9];
+  if (a_lo < a_hi) gather_b<R>(pin, nz, nr, I.bc_top, a_lo, bm, bcol, bp, fa);
+  if (!REGF && !MOMENTS && s < e) gather_b<R>(pin, nz, nr, I.bc_top, s, bm, bcol, bp, fg);
 
   for (int t = a_lo; t < e + 6; ++t) {
     if (REGF) {
@@ -372,24 +384,30 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         for (int i = 0; i < 9; ++i) fd[REGF ? a : 0][i] = fd[REGF ? a - 1 : 0][i];
     }
 #pragma unroll
-    for (int q = 4; q > 0; --q) {
-      rho_d[q] = rho_d[q - 1];
+    for (int q = 6; q > 0; --q) {
+      sg_d[q] = sg_d[q - 1];
       jz_d[q] = jz_d[q - 1];
       jr_d[q] = jr_d[q - 1];
-      kap_d[q] = kap_d[q - 1];
     }
+#pragma unroll
+    for (int q = 4; q > 0; --q) kap_d[q] = kap_d[q - 1];
     fk2z = fk1z; fk2r = fk1r; fk1z = fk0z; fk1r = fk0r;
     fc2z = fc1z; fc2r = fc1r; fc1z = fc0z; fc1r = fc0r;
+    ir2 = ir1; ir1 = ir0;
 
     // ------------------------------------------------------------------ A: row t (slot rb[0])
     {
       const int x = t;
       if (x >= a_lo && x < a_hi) {
-        R f[9];
-        gather_b<R>(pin, nz, nr, I.bc_top, x, bm, bcol, bp, f);
+        const R* f = fa;
         const R sg = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
         const R jz = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
         const R jr = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+        if (REGF) {
+#pragma unroll
+          for (int i = 0; i < 9; ++i) fd[0][i] = f[i];
+        }
+        if (x + 1 < a_hi) gather_b<R>(pin, nz, nr, I.bc_top, x + 1, bm, bcol, bp, fa);
         const double rd = I.rho_ref + (double)sg;  // rho in FP64 for the EOS
         double Pk, kap;
         eos_dev(I, rd, Pk, kap);
@@ -400,11 +418,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         L.at(R_PSI, rb[0], 0) = psi;
         if (x == 0) L.at(R_PSI, rb[1], 0) = psi;  // psi is even across the axis: row -1 = row t - 1
         if (x == 1) L.at(R_PSI, rb[3], 0) = psi;  // row -2 = row t - 3
-        if (REGF) {
-#pragma unroll
-          for (int i = 0; i < 9; ++i) fd[0][i] = f[i];
-        }
-        rho_d[0] = R(rd);
+        sg_d[0] = sg;
         jz_d[0] = jz;
         jr_d[0] = jr;
         kap_d[0] = R(kap);
@@ -414,7 +428,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         L.at(R_PSI, rb[0], 0) = L.at(R_PSI, rb[3], 0);  // row nr + 1 = row nr - 2
       }
     }
-    __syncthreads();
+    lds_barrier();
 
     // ------------------------------------------------------------------ B: row t-2 (rows t-4 .. t)
     {
@@ -450,21 +464,22 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         L.at(R_DR, rb[2], 0) = -L.at(R_DR, rb[0], 0);
       }
     }
-    __syncthreads();
+    lds_barrier();
 
     // ------------------------------------------------------------------ C: row t-4 (rows t-6 .. t-2)
     {
       const int x = t - 4;
       if (x >= c_lo && x < c_hi) {
         const Rows5 r{rb[1], rb[0], rb[4], rb[3], rb[2]};
-        const R rho = rho_d[4], jz = jz_d[4], jr = jr_d[4], kap = kap_d[4];
+        const R rho = rho_ref + sg_d[4], jz = jz_d[4], jr = jr_d[4], kap = kap_d[4];
         R fz = fk2z, fr = fk2r;
         if (I.axisym) {
           // F_axis = 3K/r [psi D_rz psi + 6A D_r psi D_z psi, psi (D_rr psi - D_r psi / r) + 6A (D_r psi)^2]
           const R drr = stencil_dr36<R, W>(L, R_DR, r) * i36;
           const R drz = stencil_dr36<R, W>(L, R_DZ, r) * i36;
           const R psi = psi_ref + L.at(R_PSI, r.s0, 0), dz = L.at(R_DZ, r.s0, 0), dr = L.at(R_DR, r.s0, 0);
-          const R ir = R(g.inv_r[x]);  // 1/r_j, uniform: a scalar load
+          const R ir = recip(R(x) + R(0.5));  // 1/r_j (uniform), carried on to stage D
+          ir0 = ir;
           const R k3 = (I.faxis_sound ? R(1.0 / 3.0) : R(3) * kap * kap) * ir;
           const R a6dr = A6 * dr;
           fz = fmad(k3, fmad(psi, drz, a6dr * dz), fz);
@@ -494,7 +509,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         L.at(R_UR, rb[4], 0) = -L.at(R_UR, rb[2], 0);
       }
     }
-    __syncthreads();
+    lds_barrier();
 
     // ------------------------------------------------------------------ D: row t-6 (rows t-8 .. t-4)
     if (!MOMENTS) {
@@ -506,11 +521,11 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
 #pragma unroll
           for (int i = 0; i < 9; ++i) f[i] = fd[REGF ? 6 : 0][i];
         } else {
-          gather_b<R>(pin, nz, nr, I.bc_top, x, bm, bcol, bp, f);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) f[i] = fg[i];
+          if (x + 1 < e) gather_b<R>(pin, nz, nr, I.bc_top, x + 1, bm, bcol, bp, fg);
         }
-        const R sg = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-        const R jz = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-        const R jr = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+        const R sg = sg_d[6], jz = jz_d[6], jr = jr_d[6];
         const R rho = rho_ref + sg;
         R m0 = R(0), H3z = R(0), H3r = R(0);
         if (I.axisym) {
@@ -519,7 +534,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
           const R druz = stencil_dr36<R, W>(L, R_UZ, r);  // 36 D_r u_z
           const R dzur = stencil_dz36<R, W>(L, R_UR, r);  // 36 D_z u_r
           const R drur = stencil_dr36<R, W>(L, R_UR, r);  // 36 D_r u_r
-          const R ir = R(g.inv_r[x]);
+          const R ir = ir2;
           const R mu36 = rho * nu * i36;
           const R ir3 = R(3) * ir;
           const R rur = rho * ur;
@@ -558,25 +573,37 @@ __device__ __forceinline__ int xcd_map(int b, int G) {
   return xcd < rem ? xcd * (q + 1) + pos : rem * (q + 1) + (xcd - rem) * q + pos;
 }
 
+// Minimum waves per SIMD asked of the register allocator: the kernel is bound by issue and
+// latency, so the register budget is set to keep enough waves resident (96 VGPRs for five
+// waves in FP32, 256 for two in FP64).  The persistent loop keeps more state live and the
+// variants that carry the populations in registers need more; they get one wave less, or
+// take what they need.
+template <typename R, bool PERSIST, bool REGF>
+struct SweepWaves {
+  static constexpr int base = REGF ? (sizeof(R) == 4 ? 3 : 1) : (sizeof(R) == 4 ? 5 : 2);
+  static constexpr int value = (PERSIST && !REGF) ? base - 1 : base;
+};
+
 template <typename R, int W, bool MOMENTS, bool PERSIST, bool REGF>
-__global__ void __launch_bounds__(W) k_sweep(SweepArgs<R> g) {
+__global__ void __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(SweepWaves<R, PERSIST, REGF>::value)))
+k_sweep(SweepArgs<R> g) {
   __shared__ R ring[RD][W + 4][NRING];
   __shared__ int s_ticket;
   const int lane = threadIdx.x;
-  char* const lds_lane = reinterpret_cast<char*>(&ring[0][lane][0]);
+  char* const lds = reinterpret_cast<char*>(&ring[0][0][0]);
   if (!PERSIST) {
     const int b = (int)blockIdx.x;
     const int item = g.xcd_swizzle ? xcd_map(b, (int)gridDim.x) : b;
-    if (item < g.n_items) run_item<R, W, MOMENTS, REGF>(g, g.items[item], lds_lane, lane);
+    if (item < g.n_items) run_item<R, W, MOMENTS, REGF>(g, g.items[item], lds, lane);
     return;
   }
   for (;;) {
     if (lane == 0) s_ticket = atomicAdd(&g.queue[0], 1);
-    __syncthreads();
+    lds_barrier();
     const int item = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform across the workgroup
-    __syncthreads();
+    lds_barrier();
     if (item >= g.n_items) break;
-    run_item<R, W, MOMENTS, REGF>(g, g.items[item], lds_lane, lane);
+    run_item<R, W, MOMENTS, REGF>(g, g.items[item], lds, lane);
   }
   if (lane == 0) {
     // The last workgroup out rewinds the queue for the next launch (no memset needed,
@@ -665,7 +692,7 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double (*sm)[K]) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   if (l == 0)
     for (int q = 0; q < K; ++q) sm[w][q] = v[q];
-  __syncthreads();
+  lds_barrier();
   if (threadIdx.x == 0) {
     for (int q = 0; q < K; ++q) {
       double s = 0.0;
