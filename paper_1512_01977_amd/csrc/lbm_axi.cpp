@@ -254,6 +254,7 @@ hipError_t enqueue_sweep(lbm_axi_s* h, bool moments, int inst_for_moments, doubl
   g.fin = static_cast<const R*>(h->fbuf[h->cur]);
   g.fout = static_cast<R*>(h->fbuf[h->cur ^ 1]);
   g.plane = h->plane;
+  g.sink = h->plane - kSinkElems;
   g.inst = h->d_inst;
   g.items = h->d_items;
   g.n_items = h->n_items;
@@ -331,6 +332,9 @@ size_t f_bytes_of(int n, const lbm_axi_params* params, int prec, long long* plan
     const long long nn = (long long)params[k].nz * params[k].nr;
     off += (nn + 63) / 64 * 64;  // every instance starts on a 256-byte boundary
   }
+  // A tail of kSinkElems per plane past the last instance: the step kernel's halo lanes
+  // direct their (discarded) stores there instead of branching around them.
+  off += kSinkElems;
   if (plane_out) *plane_out = off;
   return (size_t)off * 9 * (prec == LBM_PREC_FP32 ? 4 : 8);
 }
@@ -494,6 +498,7 @@ hipError_t enqueue_moments(lbm_axi_s* h, int k, double* mr, double* mz, double* 
   g.fin = static_cast<const R*>(h->fbuf[h->cur]);
   g.fout = static_cast<R*>(h->fbuf[h->cur ^ 1]);
   g.plane = h->plane;
+  g.sink = h->plane - kSinkElems;
   g.inst = h->d_inst;
   g.items = h->d_items;
   g.n_items = h->n_items;

@@ -37,12 +37,17 @@ struct WorkItem {
   int inst, k0, ncols, s, e;
 };
 
+// Elements at the end of every distribution plane that belong to no instance (a sink for
+// the stores of the step kernel's halo lanes); at least the widest workgroup.
+constexpr long long kSinkElems = 256;
+
 // Arguments of the fused step kernel.
 template <typename R>
 struct SweepArgs {
   const R* __restrict__ fin;   // post-collision planes of the previous step
   R* __restrict__ fout;        // post-collision planes of this step
   long long plane;             // elements between consecutive direction planes
+  long long sink;              // plane index of the sink (plane - kSinkElems)
   const InstDev* __restrict__ inst;
   const WorkItem* __restrict__ items;
   int n_items;

@@ -335,6 +335,9 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
   const Planes<R> pin = make_planes<R>(g.fin + I.base, g.plane);
   const Planes<R> pout = make_planes<R>(g.fout + I.base, g.plane);
   const unsigned bcol = col * (unsigned)sizeof(R), bm = cm * (unsigned)sizeof(R), bp = cp * (unsigned)sizeof(R);
+  // Halo lanes store into the plane's sink (past every instance, one slot per lane) rather
+  // than skipping the stores, so every wave issues the same store sequence.
+  const unsigned sink_lane = (unsigned)((g.sink - I.base) * (long long)sizeof(R)) + (unsigned)lane * (unsigned)sizeof(R);
   const int s = wi.s, e = wi.e;
   const int a_lo = max(0, s - 6), a_hi = min(nr, e + 6);
   const int b_lo = max(0, s - 4), b_hi = min(nr, e + 4);
@@ -375,6 +378,10 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
   R fa[9], fg[9];
   if (a_lo < a_hi) gather_b<R>(pin, nz, nr, I.bc_top, a_lo, bm, bcol, bp, fa);
   if (!REGF && !MOMENTS && s < e) gather_b<R>(pin, nz, nr, I.bc_top, s, bm, bcol, bp, fg);
+  if (!MOMENTS) {  // the stores of a step, to the sink, so that loop entry looks like a loop iteration
+#pragma unroll
+    for (int i = 0; i < 9; ++i) pstore(pout, i, __builtin_nondeterministic_value(R(0)), sink_lane, 0u);
+  }
 
   for (int t = a_lo; t < e + 6; ++t) {
     if (REGF) {
@@ -514,7 +521,11 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
     // ------------------------------------------------------------------ D: row t-6 (rows t-8 .. t-4)
     if (!MOMENTS) {
       const int x = t - 6;
-      if (x >= s && x < e) {
+      const bool active = x >= s && x < e;
+      R o[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) o[i] = __builtin_nondeterministic_value(R(0));
+      if (active) {
         const Rows5 r{rb[3], rb[2], rb[1], rb[0], rb[4]};
         R f[9];
         if (REGF) {
@@ -542,14 +553,14 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
           H3r = fmad(R(2) * mu36, fmad(R(-36) * ur, ir, drur), -rur * ur) * ir3;
           m0 = -rur * ir;
         }
-        R o[9];
         collide<R>(f, rho, sg, jz, jr, fc2z, fc2r, m0, H3z, H3r, omega, o);
-        if (out_lane) {
-          const unsigned orow = (unsigned)x * (unsigned)sizeof(R) * (unsigned)nz;
-#pragma unroll
-          for (int i = 0; i < 9; ++i) pstore(pout, i, o[i], bcol, orow);
-        }
       }
+      // Every iteration issues the same nine stores (to the sink while the stage idles or
+      // for halo lanes), which lets the compiler keep the prefetched loads in flight.
+      const unsigned orow = active ? (unsigned)x * (unsigned)sizeof(R) * (unsigned)nz : 0u;
+      const unsigned voff = active && out_lane ? bcol : sink_lane - orow;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) pstore(pout, i, o[i], voff, orow);
     }
     {  // row t + 1 takes the slot of row t - 4
       const int r4 = rb[4];
@@ -573,14 +584,14 @@ __device__ __forceinline__ int xcd_map(int b, int G) {
   return xcd < rem ? xcd * (q + 1) + pos : rem * (q + 1) + (xcd - rem) * q + pos;
 }
 
-// Minimum waves per SIMD asked of the register allocator: the kernel is bound by issue and
-// latency, so the register budget is set to keep enough waves resident (96 VGPRs for five
-// waves in FP32, 256 for two in FP64).  The persistent loop keeps more state live and the
-// variants that carry the populations in registers need more; they get one wave less, or
-// take what they need.
+// Minimum waves per SIMD asked of the register allocator (128 VGPRs for four waves in FP32,
+// 256 for two in FP64).  The budget must not force spills: a spill reload goes through the
+// vector memory counter and would make the wave wait for its prefetched rows.  The
+// persistent loop keeps more state live and the variants that carry the populations in
+// registers need more; they get one wave less, or take what they need.
 template <typename R, bool PERSIST, bool REGF>
 struct SweepWaves {
-  static constexpr int base = REGF ? (sizeof(R) == 4 ? 3 : 1) : (sizeof(R) == 4 ? 5 : 2);
+  static constexpr int base = REGF ? (sizeof(R) == 4 ? 3 : 1) : (sizeof(R) == 4 ? 4 : 2);
   static constexpr int value = (PERSIST && !REGF) ? base - 1 : base;
 };
 
