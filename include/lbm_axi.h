@@ -52,7 +52,7 @@ typedef int32_t lbm_status;
 #define LBM_ERR_HIP (-3)         /* a HIP runtime call failed */
 #define LBM_ERR_EOS_DOMAIN (-4)  /* rho <= 0 or rho/3 - P_k < 0 (psi not real) on some node */
 #define LBM_ERR_NONFINITE (-5)   /* a non-finite value appeared */
-#define LBM_ERR_UNSUPPORTED (-6) /* valid request this build does not implement */
+#define LBM_ERR_UNSUPPORTED (-6) /* valid request outside what the library supports (see calls) */
 
 typedef enum { LBM_EOS_IDEAL = 0, LBM_EOS_VDW = 1, LBM_EOS_CS = 2 } lbm_eos_kind;
 typedef enum { LBM_TOP_FREE_SLIP = 0, LBM_TOP_NO_SLIP = 1 } lbm_top_bc;
@@ -92,10 +92,14 @@ const char* lbm_axi_status_string(lbm_status s);
 
 /* ---------------------------------------------------------------- host helpers */
 
-/* Critical point of the EOS in p (p->T ignored); vdW and CS only. */
+/* Critical point of the EOS in p (p->T ignored): dP/drho = d2P/drho2 = 0 (Sec. 2.3 for
+ * vdW; CS in the same slot).  Outputs are host scalars.  LBM_ERR_ARG for NULL pointers,
+ * the ideal gas (no critical point) or non-positive CS coefficients. */
 lbm_status lbm_axi_eos_critical(const lbm_axi_params* p, double* rho_c, double* T_c, double* P_c);
 
-/* Maxwell equal-area coexistence densities and saturation pressure at p->T < T_c. */
+/* Maxwell equal-area coexistence densities and saturation pressure at p->T < T_c (the
+ * densities Sec. 2.3 compares the EDM coexistence curve with).  Outputs are host scalars.
+ * LBM_ERR_ARG for NULL pointers, the ideal gas, or T >= T_c. */
 lbm_status lbm_axi_eos_coexistence(const lbm_axi_params* p, double* rho_v, double* rho_l,
                                    double* p_sat);
 
@@ -104,21 +108,30 @@ lbm_status lbm_axi_eos_coexistence(const lbm_axi_params* p, double* rho_v, doubl
 /* Single instance: allocate device state and set f = E(rho0, u0) (eq. lbm's
  * equilibrium, Sec. 2.1) as the populations after streaming at t = 0.
  * rho0: host [nr][nz], required; uz0, ur0: host [nr][nz] or NULL for 0.
- * precision: lbm_precision.  stream: hipStream_t, NULL = the library creates its own. */
+ * precision: lbm_precision.  stream: hipStream_t, NULL = the library creates its own.
+ * Errors: LBM_ERR_ARG (NULL out/rho0, nz < 1, nr < 4, nz*nr > 2^31, tau <= 1/2, unknown
+ * eos/bc/flag, non-finite A, gz or T, CS b <= 0, lambda <= 0 for a non-ideal EOS);
+ * LBM_ERR_NONFINITE / LBM_ERR_EOS_DOMAIN (rho0 non-finite, <= 0, or psi not real);
+ * LBM_ERR_UNSUPPORTED (three direction planes would span 4 GiB or more: the step kernel
+ * addresses them with 32-bit offsets); LBM_ERR_ALLOC; LBM_ERR_HIP.  *out is NULL on error. */
 lbm_status lbm_axi_init(const lbm_axi_params* p, int32_t precision, const double* rho0,
                         const double* uz0, const double* ur0, void* stream, lbm_axi_t* out);
 
 /* n independent instances (uneven sizes and parameters) advanced together by one
- * launch per step.  params[k] and rho0[k] (host [nr_k][nz_k]) describe instance k. */
+ * launch per step.  params[k] and rho0[k] (host [nr_k][nz_k]) describe instance k.
+ * Errors as lbm_axi_init, for any instance (n < 1: LBM_ERR_ARG). */
 lbm_status lbm_axi_batch_init(int32_t n, const lbm_axi_params* params, int32_t precision,
                               const double* const* rho0, void* stream, lbm_axi_t* out);
 
-/* Device bytes needed for the two distribution buffers of an n-instance batch. */
+/* Device bytes needed for the two distribution buffers of an n-instance batch (host
+ * arithmetic only).  Errors: LBM_ERR_ARG (as lbm_axi_batch_init's parameter checks),
+ * LBM_ERR_UNSUPPORTED (the layout exceeds the 32-bit plane offsets; nothing to allocate). */
 lbm_status lbm_axi_workspace_bytes(int32_t n, const lbm_axi_params* params, int32_t precision,
                                    size_t* bytes);
 
 /* As lbm_axi_batch_init, but the distribution buffers live in a caller-owned
- * device workspace of at least lbm_axi_workspace_bytes bytes (256-byte aligned). */
+ * device workspace of at least lbm_axi_workspace_bytes bytes (256-byte aligned).  The
+ * caller keeps it alive until lbm_axi_destroy.  LBM_ERR_ALLOC if it is too small. */
 lbm_status lbm_axi_batch_init_ws(int32_t n, const lbm_axi_params* params, int32_t precision,
                                  const double* const* rho0, void* stream, void* workspace,
                                  size_t workspace_bytes, lbm_axi_t* out);
@@ -128,7 +141,10 @@ void lbm_axi_destroy(lbm_axi_t h);
 
 /* ---------------------------------------------------------------- time stepping */
 
-/* Enqueue nsteps >= 0 time steps of every instance on the handle's stream. */
+/* Enqueue nsteps >= 0 time steps of every instance on the handle's stream (Sec. 2:
+ * streaming, moments, EOS and psi, F_K + F_axis, h_i, exact-difference BGK).  Returns
+ * before the steps run; LBM_ERR_ARG for a NULL handle or nsteps < 0, LBM_ERR_HIP if a
+ * launch fails.  Device-side errors surface at the next synchronising call. */
 lbm_status lbm_axi_step(lbm_axi_t h, int64_t nsteps);
 
 /* As lbm_axi_step, then wait; *ms receives the HIP-event time of the launches
@@ -147,7 +163,8 @@ lbm_status lbm_axi_set_graph_chunk(lbm_axi_t h, int32_t chunk);
 
 /* ---------------------------------------------------------------- observables (synchronising) */
 
-/* rho and the physical velocity u = (j + F/2)/rho of instance k; host [nr][nz] outputs. */
+/* rho and the physical velocity u = (j + F/2)/rho (Sec. 2.1) of instance k; host [nr][nz]
+ * outputs (caller-owned).  LBM_ERR_ARG for a bad k or NULL output; device errors as sync. */
 lbm_status lbm_axi_moments(lbm_axi_t h, int32_t k, double* rho, double* uz, double* ur);
 
 /* mass[k] = sum over nodes of 2 pi r_j rho, FP64, deterministic; mass is host [n]. */

@@ -324,6 +324,10 @@ lbm_status read_err(lbm_axi_s* h) {
   return LBM_OK;
 }
 
+// The step kernel addresses three direction planes per buffer descriptor with 32-bit
+// byte offsets, so three planes must span less than 4 GiB.
+bool offsets_fit(long long plane, int esize) { return 3.0 * (double)plane * (double)esize < 4294967296.0; }
+
 size_t f_bytes_of(int n, const lbm_axi_params* params, int prec, long long* plane_out,
                   std::vector<long long>* bases) {
   long long off = 0;
@@ -424,8 +428,7 @@ lbm_status create(int n, const lbm_axi_params* params, int prec, const double* c
   h->esize = prec == LBM_PREC_FP32 ? 4 : 8;
   h->prm.assign(params, params + n);
   const size_t fb = f_bytes_of(n, params, prec, &h->plane, &h->base);
-  // the step kernel addresses three direction planes per buffer descriptor (32-bit offsets)
-  if (3.0 * (double)h->plane * (double)h->esize >= 4294967296.0) {
+  if (!offsets_fit(h->plane, h->esize)) {
     delete h;
     return LBM_ERR_UNSUPPORTED;
   }
@@ -542,7 +545,14 @@ lbm_status lbm_axi_eos_coexistence(const lbm_axi_params* p, double* rho_v, doubl
 lbm_status lbm_axi_workspace_bytes(int32_t n, const lbm_axi_params* params, int32_t precision, size_t* bytes) {
   if (n < 1 || !params || !bytes) return LBM_ERR_ARG;
   if (precision != LBM_PREC_FP64 && precision != LBM_PREC_FP32) return LBM_ERR_ARG;
-  *bytes = 2 * f_bytes_of(n, params, precision, nullptr, nullptr);
+  for (int k = 0; k < n; ++k) {
+    lbm_status s = check_params(params[k]);
+    if (s != LBM_OK) return s;
+  }
+  long long plane = 0;
+  const size_t fb = f_bytes_of(n, params, precision, &plane, nullptr);
+  if (!offsets_fit(plane, precision == LBM_PREC_FP32 ? 4 : 8)) return LBM_ERR_UNSUPPORTED;
+  *bytes = 2 * fb;
   return LBM_OK;
 }
 

@@ -1,0 +1,97 @@
+"""The benchmark workloads at full size, in the launch shapes the tuner picks for them
+(the configuration bench.py times), against the oracle on the same seeded inputs.
+
+FP64 is held to the 1e-10 bar of the small-grid parity tests.  The FP32 form's field
+errors against the FP64 oracle are printed and bounded at about ten times what FP32
+rounding gives here (unit roundoff 6e-8, a few times 1e-8 per step in rho; measured
+1.1e-6 in rho and 7e-6 of the velocity scale after 20 steps); its tolerances on the
+physics (Laplace pressure, oscillation frequency, mass) are tested elsewhere.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+ENSEMBLE_STEPS = 20
+LARGE_STEPS = 2
+
+
+def oparams(p):
+    return O.Params(nz=p.nz, nr=p.nr, tau=p.tau, eos=p.eos, T=p.T, eos_a=p.eos_a, eos_b=p.eos_b,
+                    eos_R=p.eos_R, lam=p.lam, A=p.A, axisym=p.axisym, faxis_sound=p.faxis_sound,
+                    bc_top=p.bc_top, gz=p.gz)
+
+
+def oracle_moments(p, rho0, steps):
+    q = oparams(p)
+    f = O.init(q, rho0)
+    O.step(q, f, steps)
+    return O.moments(q, f)
+
+
+def field_errors(g, o):
+    rg, uzg, urg = g
+    ro, uzo, uro = o
+    uscale = max(np.abs(uzo).max(), np.abs(uro).max(), 1e-300)
+    return (float(np.abs(rg - ro).max() / np.abs(ro).max()),
+            float(max(np.abs(uzg - uzo).max(), np.abs(urg - uro).max()) / uscale))
+
+
+def run_gpu(wl, steps, chunk):
+    from paper_1512_01977_amd import lbm, tuning
+    single = len(wl.params) == 1
+    with lbm.LbmAxi(wl.params[0] if single else wl.params, wl.rho0[0] if single else wl.rho0,
+                    precision=wl.precision) as sim:
+        launch = tuning.choose_launch(sim, wl, tune=True, log=lambda *a: print(*a, flush=True))
+        print("launch", launch, flush=True)
+        if chunk:
+            sim.set_graph_chunk(chunk)
+        sim.step(steps)
+        assert not sim.errors().any()
+        return [sim.moments(k) for k in range(len(wl.params))]
+
+
+@pytest.fixture(scope="module")
+def ensemble_oracle():
+    from paper_1512_01977_amd import workloads
+    wl = workloads.ensemble(precision=0)
+    return [oracle_moments(p, r, ENSEMBLE_STEPS) for p, r in zip(wl.params, wl.rho0)]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ensemble_full_size_tuned_launch(precision, ensemble_oracle):
+    # All 256 members (12 889 106 nodes, nr 32..256, ragged strips) after 20 steps run as
+    # two 10-step graph replays, in the tuned shape of this precision.
+    from paper_1512_01977_amd import workloads
+    wl = workloads.ensemble(precision=precision)
+    got = run_gpu(wl, ENSEMBLE_STEPS, 10)
+    errs = np.array([field_errors(g, o) for g, o in zip(got, ensemble_oracle)])
+    print(f"ensemble precision {precision}: max rho err {errs[:, 0].max():.3e}, "
+          f"max u err {errs[:, 1].max():.3e} (of the member's velocity scale)", flush=True)
+    if precision == 0:
+        assert errs.max() <= 1e-10
+    else:
+        assert errs[:, 0].max() <= 1e-5 and errs[:, 1].max() <= 1e-4
+
+
+@pytest.fixture(scope="module")
+def large_oracle():
+    from paper_1512_01977_amd import workloads
+    wl = workloads.large_droplet(precision=0)
+    return oracle_moments(wl.params[0], wl.rho0[0], LARGE_STEPS)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_large_domain_full_size_tuned_launch(precision, large_oracle):
+    # The 16384 x 8192 droplet (134 217 728 nodes) after two steps, every node.
+    from paper_1512_01977_amd import workloads
+    wl = workloads.large_droplet(precision=precision)
+    (g,) = run_gpu(wl, LARGE_STEPS, 0)
+    er, eu = field_errors(g, large_oracle)
+    print(f"large precision {precision}: rho err {er:.3e}, u err {eu:.3e}", flush=True)
+    if precision == 0:
+        assert max(er, eu) <= 1e-10
+    else:
+        assert er <= 5e-6 and eu <= 5e-5

@@ -89,3 +89,24 @@ def test_tuning_size_class_keys():
     b = tuning.size_class([lbm.Params(nz=16384, nr=8192)], 0)
     c = tuning.size_class([lbm.Params(nz=64, nr=32)] * 256, 1)
     assert a != b and a.startswith("gfx950:f32:single") and c.startswith("gfx950:f32:batch256")
+
+
+def test_workspace_sizing_and_offset_limit():
+    # Two buffers of nine planes, each plane padded per instance to 64 elements plus a
+    # 256-element sink; layouts whose three planes would span 4 GiB are refused up front.
+    import ctypes
+    from paper_1512_01977_amd import lbm
+    L = lbm.lib()
+
+    def ws(nz, nr, prec):
+        p = (lbm.lbm_axi_params * 1)(lbm.Params(nz=nz, nr=nr, eos=lbm.EOS_CS, T=0.05).c())
+        nb = ctypes.c_size_t()
+        return L.lbm_axi_workspace_bytes(1, p, prec, ctypes.byref(nb)), nb.value
+
+    st, nb = ws(16384, 8192, lbm.PREC_FP64)
+    assert st == 0 and nb == 2 * 9 * 8 * (16384 * 8192 + 256)
+    st, nb = ws(100, 7, lbm.PREC_FP32)
+    assert st == 0 and nb == 2 * 9 * 4 * (704 + 256)
+    assert ws(16384, 11000, lbm.PREC_FP64)[0] == -6     # 3 * plane * 8 B >= 4 GiB
+    assert ws(16384, 11000, lbm.PREC_FP32)[0] == 0
+    assert ws(16384, 3, lbm.PREC_FP32)[0] == -1         # nr < 4
