@@ -32,8 +32,9 @@
  *     lbm_axi_destroy and the library never frees it;
  *   - a handle is bound to one HIP stream and is not thread-safe;
  *   - lbm_axi_step is asynchronous; errors raised on the device (EOS domain,
- *     non-finite values) are reported by the next synchronising call
- *     (lbm_axi_sync, _moments, _mass, _laplace, _get_f).
+ *     non-finite values) are reported by the next synchronising call: lbm_axi_sync,
+ *     _mass and _laplace report them for any instance, _moments and _get_f for the
+ *     instance they read (instances are independent).
  */
 #ifndef LBM_AXI_H
 #define LBM_AXI_H
@@ -164,7 +165,9 @@ lbm_status lbm_axi_set_graph_chunk(lbm_axi_t h, int32_t chunk);
 /* ---------------------------------------------------------------- observables (synchronising) */
 
 /* rho and the physical velocity u = (j + F/2)/rho (Sec. 2.1) of instance k; host [nr][nz]
- * outputs (caller-owned).  LBM_ERR_ARG for a bad k or NULL output; device errors as sync. */
+ * outputs (caller-owned).  LBM_ERR_ARG for a bad k or NULL output; LBM_ERR_EOS_DOMAIN or
+ * LBM_ERR_NONFINITE if instance k has left the EOS domain (the outputs are then filled but
+ * meaningless). */
 lbm_status lbm_axi_moments(lbm_axi_t h, int32_t k, double* rho, double* uz, double* ur);
 
 /* mass[k] = sum over nodes of 2 pi r_j rho, FP64, deterministic; mass is host [n]. */

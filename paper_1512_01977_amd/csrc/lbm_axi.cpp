@@ -315,9 +315,10 @@ lbm_status enqueue_steps(lbm_axi_s* h, int64_t nsteps) {
   return enqueue_steps_eager(h, nsteps);
 }
 
-lbm_status read_err(lbm_axi_s* h) {
+// The sticky device error bits of the handle (k < 0: any instance) or of instance k.
+lbm_status read_err(lbm_axi_s* h, int k = -1) {
   int e = 0;
-  HIPCHK(hipMemcpyAsync(&e, h->d_err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(&e, h->d_err + (k < 0 ? 0 : 1 + k), sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   if (e & 2) return LBM_ERR_NONFINITE;
   if (e & 1) return LBM_ERR_EOS_DOMAIN;
@@ -690,7 +691,7 @@ lbm_status lbm_axi_moments(lbm_axi_t h, int32_t k, double* rho, double* uz, doub
   (void)hipFree(d_items);
   (void)hipFree(tmp);
   if (st != LBM_OK) return st;
-  return read_err(h);
+  return read_err(h, k);
 }
 
 static lbm_status reduce(lbm_axi_t h, int K, double* out) {
@@ -742,7 +743,7 @@ lbm_status lbm_axi_get_f(lbm_axi_t h, int32_t k, double* f) {
     st = LBM_ERR_HIP;
   (void)hipFree(tmp);
   if (st != LBM_OK) return st;
-  return read_err(h);
+  return read_err(h, k);
 }
 
 lbm_status lbm_axi_set_f(lbm_axi_t h, int32_t k, const double* f) {

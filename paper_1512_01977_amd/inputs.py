@@ -62,6 +62,15 @@ def gaussian_pulse(nz: int, nr: int, rho0: float, amplitude: float, r0: float,
     return np.ascontiguousarray(np.repeat(prof[:, None], nz, axis=1))
 
 
+def slab(nz: int, nr: int, rho_v: float, rho_l: float, z0: float, z1: float,
+         width: float = 5.0) -> np.ndarray:
+    """Planar liquid layer between z0 and z1 (uniform in r), tanh interfaces of the given
+    width: rho = rho_v + (rho_l - rho_v)/2 [tanh(2 (z - z0)/width) - tanh(2 (z - z1)/width)]."""
+    z = np.arange(nz, dtype=np.float64)
+    prof = rho_v + 0.5 * (rho_l - rho_v) * (np.tanh(2.0 * (z - z0) / width) - np.tanh(2.0 * (z - z1) / width))
+    return np.ascontiguousarray(np.repeat(prof[None, :], nr, axis=0))
+
+
 @dataclass
 class Instance:
     """One member of a batched droplet ensemble."""

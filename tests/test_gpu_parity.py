@@ -259,6 +259,30 @@ def test_device_reports_eos_domain_error():
         assert e.value.code in (-4, -5)
 
 
+def test_error_in_one_member_leaves_the_others_readable():
+    # A batch of a failing member (as above) and a sound one: the handle-wide sync reports
+    # the error, the flags name the failing member only, and the sound member still reads
+    # back bitwise equal to its single-instance run.
+    L = lbm()
+    bad = base(64, 32, T=0.485 * base(1, 1)["T"] / 0.8, tau=0.8)
+    good = base(64, 32)
+    rb, rg = droplet_rho(bad, 10.0), droplet_rho(good, 10.0, seed=3)
+    with L.LbmAxi([gpu_params(bad), gpu_params(good)], [rb, rg]) as sim:
+        sim.step(200)
+        with pytest.raises(L.LbmError):
+            sim.sync()
+        flags = sim.errors()
+        assert flags[0] != 0 and flags[1] == 0
+        with pytest.raises(L.LbmError):
+            sim.moments(0)
+        mg = sim.moments(1)
+        fg = sim.get_f(1)
+    with L.LbmAxi(gpu_params(good), rg) as one:
+        one.step(200)
+        assert np.array_equal(one.get_f(), fg)
+        assert all(np.array_equal(a, b) for a, b in zip(one.moments(), mg))
+
+
 def test_host_rejects_bad_input():
     L = lbm()
     d = base(16, 8, T=0.485 * base(1, 1)["T"] / 0.8)
