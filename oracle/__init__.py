@@ -21,6 +21,7 @@ _LIB_PATH = os.path.join(_HERE, "liblbm_oracle.so")
 
 EOS_IDEAL, EOS_VDW, EOS_CS = 0, 1, 2
 TOP_FREE_SLIP, TOP_NO_SLIP = 0, 1
+FORCING_EDM, FORCING_GUO = 0, 1
 
 # D2Q9 set as numbered in lbm_oracle.h (c_z, c_r), Sec. 2.1.
 CZ = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
@@ -49,6 +50,7 @@ class _Params(ctypes.Structure):
         ("bc_top", ctypes.c_int32),
         ("hr_printed_sign", ctypes.c_int32),
         ("gz", ctypes.c_double),
+        ("forcing", ctypes.c_int32),
     ]
 
 
@@ -70,11 +72,12 @@ class Params:
     bc_top: int = TOP_FREE_SLIP
     hr_printed_sign: int = 0
     gz: float = 0.0
+    forcing: int = 0
 
     def c(self) -> _Params:
         return _Params(self.nz, self.nr, self.tau, self.eos, self.T, self.eos_a, self.eos_b,
                        self.eos_R, self.lam, self.A, self.axisym, self.faxis_sound, self.bc_top,
-                       self.hr_printed_sign, self.gz)
+                       self.hr_printed_sign, self.gz, self.forcing)
 
 
 _lib = None
@@ -99,6 +102,8 @@ def lib() -> ctypes.CDLL:
         L.lbm_oracle_force_psi.argtypes = [P, dp, dp, dp, dp]
         L.lbm_oracle_source.argtypes = [P] + [ctypes.c_double] * 7 + [dp]
         L.lbm_oracle_source.restype = None
+        L.lbm_oracle_guo_source.argtypes = [ctypes.c_double] * 5 + [dp]
+        L.lbm_oracle_guo_source.restype = None
         L.lbm_oracle_init.argtypes = [P, dp, dp, dp, dp]
         L.lbm_oracle_step.argtypes = [P, dp, ctypes.c_int64]
         L.lbm_oracle_moments.argtypes = [P, dp, dp, dp, dp]
@@ -173,6 +178,13 @@ def source(p: Params, r, rho, uz, ur, dr_uz, dz_ur, dr_ur) -> np.ndarray:
     h = np.zeros(9)
     lib().lbm_oracle_source(ctypes.byref(p.c()), r, rho, uz, ur, dr_uz, dz_ur, dr_ur, _ptr(h))
     return h
+
+
+def guo_source(tau, uz, ur, Fz, Fr) -> np.ndarray:
+    """Guo's S_i of Sec. 2.1 at one node."""
+    S = np.zeros(9)
+    lib().lbm_oracle_guo_source(tau, uz, ur, Fz, Fr, _ptr(S))
+    return S
 
 
 def init(p: Params, rho0: np.ndarray, uz0=None, ur0=None) -> np.ndarray:

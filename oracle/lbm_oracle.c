@@ -11,8 +11,10 @@
  *
  * Readings of passages the paper leaves open (each is a flag or a stated
  * choice here):
- *  - Force application: the exact-difference method named in Sec. 2.3 (the
- *    Guo term printed in Sec. 2.1 is not used).
+ *  - Force application: the exact-difference method named in Sec. 2.3 by
+ *    default; Guo's term printed in Sec. 2.1 as the alternative (flag
+ *    `forcing`), with its garbled second term read as (c_i.u)(c_i.F)/c_s^4 and
+ *    BGK relaxing toward E(rho, u) at the physical velocity u = (j + F/2)/rho.
  *  - h_i (Sec. 2.2) is evaluated from the fields at (x, t).
  *  - H_z, H_r (eq. axihz) are node scalars; the stray c_iz, c_ir factors in
  *    the printed equation are dropped, otherwise sum_i h_i would not equal
@@ -335,6 +337,17 @@ void lbm_oracle_source(const lbm_oracle_params* p, double r, double rho, double 
     h[i] = WGT[i] * (-rho * ur / r + 3.0 * (CZ[i] * Hz + CR[i] * Hr));
 }
 
+void lbm_oracle_guo_source(double tau, double uz, double ur, double Fz, double Fr, double S[9]) {
+  /* Sec. 2.1 with c_s^2 = 1/3: (c_i - u).F / c_s^2 + (c_i.u)(c_i.F) / c_s^4 */
+  double pre = 1.0 - 0.5 / tau;
+  for (int i = 0; i < 9; ++i) {
+    double cu = CZ[i] * uz + CR[i] * ur;
+    double cF = CZ[i] * Fz + CR[i] * Fr;
+    double cmuF = (CZ[i] - uz) * Fz + (CR[i] - ur) * Fr;
+    S[i] = WGT[i] * pre * (3.0 * cmuF + 9.0 * cu * cF);
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Whole step                                                                 */
 /* ------------------------------------------------------------------------ */
@@ -345,6 +358,7 @@ static int check_params(const lbm_oracle_params* p) {
   if (!(p->tau > 0.5)) return ERR_ARG;
   if (p->eos < ORACLE_EOS_IDEAL || p->eos > ORACLE_EOS_CS) return ERR_ARG;
   if (p->bc_top != ORACLE_TOP_FREE_SLIP && p->bc_top != ORACLE_TOP_NO_SLIP) return ERR_ARG;
+  if (p->forcing != ORACLE_FORCING_EDM && p->forcing != ORACLE_FORCING_GUO) return ERR_ARG;
   return 0;
 }
 
@@ -447,15 +461,25 @@ static int one_step(const lbm_oracle_params* p, double* f, double* fs, fields* w
       double rho = w->rho[x];
       double ubz = w->jz[x] / rho, ubr = w->jr[x] / rho;
       double e0[9], e1[9], h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-      /* exact-difference method: Delta f_i = E_i(rho, u_b + F dt/rho) - E_i(rho, u_b) */
-      lbm_oracle_equilibrium(rho, ubz, ubr, e0);
-      lbm_oracle_equilibrium(rho, ubz + w->Fz[x] / rho, ubr + w->Fr[x] / rho, e1);
       if (p->axisym)
         lbm_oracle_source(p, radius(j), rho, w->uz[x], w->ur[x], druz[x], dzur[x], drur[x], h);
-      for (int i = 0; i < 9; ++i) {
-        double fi = f[i * n + x];
-        /* eq. (lbm) with the axisymmetric source of Sec. 2.2 */
-        fs[i * n + x] = fi + omega * (e0[i] - fi) + (e1[i] - e0[i]) + h[i];
+      if (p->forcing == ORACLE_FORCING_EDM) {
+        /* exact-difference method: Delta f_i = E_i(rho, u_b + F dt/rho) - E_i(rho, u_b) */
+        lbm_oracle_equilibrium(rho, ubz, ubr, e0);
+        lbm_oracle_equilibrium(rho, ubz + w->Fz[x] / rho, ubr + w->Fr[x] / rho, e1);
+        for (int i = 0; i < 9; ++i) {
+          double fi = f[i * n + x];
+          /* eq. (lbm) with the axisymmetric source of Sec. 2.2 */
+          fs[i * n + x] = fi + omega * (e0[i] - fi) + (e1[i] - e0[i]) + h[i];
+        }
+      } else {
+        /* Guo (Sec. 2.1): BGK toward E(rho, u) at the physical velocity, plus S_i */
+        lbm_oracle_equilibrium(rho, w->uz[x], w->ur[x], e0);
+        lbm_oracle_guo_source(p->tau, w->uz[x], w->ur[x], w->Fz[x], w->Fr[x], e1);
+        for (int i = 0; i < 9; ++i) {
+          double fi = f[i * n + x];
+          fs[i * n + x] = fi + omega * (e0[i] - fi) + e1[i] + h[i];
+        }
       }
     }
   }

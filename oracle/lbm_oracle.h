@@ -31,6 +31,7 @@ extern "C" {
 
 enum { ORACLE_EOS_IDEAL = 0, ORACLE_EOS_VDW = 1, ORACLE_EOS_CS = 2 };
 enum { ORACLE_TOP_FREE_SLIP = 0, ORACLE_TOP_NO_SLIP = 1 };
+enum { ORACLE_FORCING_EDM = 0, ORACLE_FORCING_GUO = 1 };
 
 typedef struct {
   int32_t nz, nr;          /* nz >= 1, nr >= 4 */
@@ -45,6 +46,7 @@ typedef struct {
   int32_t bc_top;          /* ORACLE_TOP_* at r = nr */
   int32_t hr_printed_sign; /* 0: H_r with -u_r/r (follows C_r); 1: as printed, +u_r/r */
   double gz;               /* uniform body-force density along z */
+  int32_t forcing;         /* ORACLE_FORCING_EDM (Sec. 2.3) or ORACLE_FORCING_GUO (Sec. 2.1) */
 } lbm_oracle_params;
 
 /* Equation of state at density rho: pressure P_k, kappa = dP_k/drho and the
@@ -77,6 +79,11 @@ int lbm_oracle_force_psi(const lbm_oracle_params* p, const double* psi, const do
  * velocity u and the three velocity derivatives it needs. */
 void lbm_oracle_source(const lbm_oracle_params* p, double r, double rho, double uz, double ur,
                        double dr_uz, double dz_ur, double dr_ur, double h[9]);
+
+/* Guo's forcing term S_i of Sec. 2.1 at one node: w_i (1 - 1/(2 tau)) [3 (c_i - u).F +
+ * 9 (c_i.u)(c_i.F)], u the physical velocity (the printed second term is read as
+ * (c_i.u)(c_i.F)/c_s^4). */
+void lbm_oracle_guo_source(double tau, double uz, double ur, double Fz, double Fr, double S[9]);
 
 /* f = E(rho0, u_b0): post-streaming populations at t = 0.  uz0/ur0 may be NULL (0). */
 int lbm_oracle_init(const lbm_oracle_params* p, const double* rho0, const double* uz0,

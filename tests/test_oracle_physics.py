@@ -80,6 +80,59 @@ def test_body_force_adds_momentum(axisym):
     assert np.allclose(jz, 25 * g, rtol=1e-10)
 
 
+def test_guo_source_moments():
+    # Guo's term (Sec. 2.1, second term read as (c.u)(c.F)/c_s^4) has the moments that make
+    # the scheme second order: sum S = 0, sum c S = (1 - 1/2tau) F,
+    # sum c c S = (1 - 1/2tau)(u F + F u); a dropped term or a sign error breaks one of them.
+    rng = np.random.default_rng(5)
+    for _ in range(5):
+        tau = rng.uniform(0.55, 2.0)
+        u = rng.uniform(-0.1, 0.1, 2)
+        F = rng.uniform(-1e-2, 1e-2, 2)
+        S = O.guo_source(tau, u[0], u[1], F[0], F[1])
+        c = np.stack([O.CZ, O.CR], axis=1).astype(float)
+        pre = 1 - 0.5 / tau
+        assert abs(S.sum()) < 1e-16
+        assert np.allclose(c.T @ S, pre * F, rtol=1e-13, atol=1e-18)
+        second = np.einsum("ia,ib,i->ab", c, c, S)
+        assert np.allclose(second, pre * (np.outer(u, F) + np.outer(F, u)), rtol=1e-12, atol=1e-18)
+
+
+@pytest.mark.parametrize("axisym", [0, 1])
+def test_guo_forcing_adds_momentum_and_keeps_mass(axisym):
+    # With Guo's forcing BGK relaxes toward E(rho, u), u = (j + F/2)/rho, and S_i adds
+    # (1 - 1/2tau) F: the momentum still grows by F per step, the mass is unchanged.
+    g = 1e-6
+    p = ideal(10, 6, gz=g, axisym=axisym, forcing=O.FORCING_GUO)
+    f = O.init(p, np.full((6, 10), 0.9))
+    m0 = f.sum()
+    O.step(p, f, 25)
+    jz = (O.CZ[:, None, None] * f).sum(0)
+    assert np.allclose(jz, 25 * g, rtol=1e-10)
+    assert f.sum() == pytest.approx(m0, rel=1e-14)
+
+
+def test_guo_forcing_differs_from_edm_and_keeps_symmetry():
+    # Same droplet, both force applications: Guo keeps the z-mirror symmetry and the 2-D mass,
+    # and its state differs from the exact-difference one (the F F/rho term of the EDM
+    # increment is absent).
+    out = {}
+    for forcing in (O.FORCING_EDM, O.FORCING_GUO):
+        p = cs_params(64, 24, axisym=0, forcing=forcing)
+        rv, rl, _ = O.coexistence(p)
+        rho0 = inputs.droplet(64, 24, rv, rl, 9.0, zc=32.0, eps=0.15)
+        f = O.init(p, rho0)
+        m0 = f.sum()
+        O.step(p, f, 150)
+        assert f.sum() == pytest.approx(m0, rel=1e-12)
+        rho, uz, ur = O.moments(p, f)
+        mirror = (-np.arange(64)) % 64
+        assert np.abs(rho - rho[:, mirror]).max() < 1e-12
+        assert np.abs(uz + uz[:, mirror]).max() < 1e-12
+        out[forcing] = rho
+    assert np.abs(out[0] - out[1]).max() > 1e-6
+
+
 def test_z_mirror_symmetry_is_preserved():
     p = cs_params(64, 24, axisym=1)
     rv, rl, _ = O.coexistence(p)
