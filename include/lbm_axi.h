@@ -58,6 +58,7 @@ typedef int32_t lbm_status;
 typedef enum { LBM_EOS_IDEAL = 0, LBM_EOS_VDW = 1, LBM_EOS_CS = 2 } lbm_eos_kind;
 typedef enum { LBM_TOP_FREE_SLIP = 0, LBM_TOP_NO_SLIP = 1 } lbm_top_bc;
 typedef enum { LBM_PREC_FP64 = 0, LBM_PREC_FP32 = 1 } lbm_precision;
+typedef enum { LBM_FORCING_EDM = 0, LBM_FORCING_GUO = 1 } lbm_forcing;
 
 /* One simulation instance.  Sec. 2 of the paper defines every field except
  * the Carnahan-Starling coefficients, which follow the usual form
@@ -74,6 +75,10 @@ typedef struct {
   int32_t faxis_sound;       /* 0: F_axis uses c_k^4 = (dP_k/drho)^2 (Sec. 2.3); 1: c_s^4 = 1/9 */
   int32_t bc_top;            /* lbm_top_bc at r = nr */
   double gz;                 /* uniform body-force density along z added to F */
+  int32_t forcing;           /* lbm_forcing: LBM_FORCING_EDM, the exact-difference method the
+                                paper relies on (Sec. 2.3, default), or LBM_FORCING_GUO, the
+                                source term printed in Sec. 2.1 (its second term read as
+                                (c_i.u)(c_i.F)/c_s^4, BGK toward E(rho, u), u = (j + F/2)/rho) */
 } lbm_axi_params;
 
 /* Launch shape of the fused step kernel (chosen by lbm_axi_autotune or set by hand). */
@@ -111,7 +116,7 @@ lbm_status lbm_axi_eos_coexistence(const lbm_axi_params* p, double* rho_v, doubl
  * rho0: host [nr][nz], required; uz0, ur0: host [nr][nz] or NULL for 0.
  * precision: lbm_precision.  stream: hipStream_t, NULL = the library creates its own.
  * Errors: LBM_ERR_ARG (NULL out/rho0, nz < 1, nr < 4, nz*nr > 2^31, tau <= 1/2, unknown
- * eos/bc/flag, non-finite A, gz or T, CS b <= 0, lambda <= 0 for a non-ideal EOS);
+ * eos/bc/forcing/flag, non-finite A, gz or T, CS b <= 0, lambda <= 0 for a non-ideal EOS);
  * LBM_ERR_NONFINITE / LBM_ERR_EOS_DOMAIN (rho0 non-finite, <= 0, or psi not real);
  * LBM_ERR_UNSUPPORTED (three direction planes would span 4 GiB or more: the step kernel
  * addresses them with 32-bit offsets); LBM_ERR_ALLOC; LBM_ERR_HIP.  *out is NULL on error. */

@@ -9,9 +9,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm_axi.so")
 SOURCES = ["lbm_kernels.hip", "lbm_axi.cpp", "eos_host.cpp"]
-# No fast-math (the FP64 path is compared with an FP64 reference); packed FP32
-# instructions are disabled.
-FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-fno-fast-math",
+# No fast-math (the FP64 path is compared with an FP64 reference); multiply-adds are fused
+# only within one expression (-ffp-contract=on), so that every kernel instantiation rounds
+# the same arithmetic the same way; packed FP32 instructions are disabled.
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-fno-fast-math", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-Wall"]
 

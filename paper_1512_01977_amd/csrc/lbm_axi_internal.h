@@ -17,7 +17,7 @@ double eos_psi(const lbm_axi_params& p, double rho);  // sqrt(rho/3 - P_k), 0 fo
 struct InstDev {
   long long base;    // index of node (0, 0) of the instance inside every distribution plane
   int nz, nr;
-  int eos, axisym, faxis_sound, bc_top;
+  int eos, axisym, faxis_sound, bc_top, forcing;
   // EOS in the form the kernels evaluate (FP64 in every precision):
   //   Carnahan-Starling  P = c1 rho n(e) / (1 - e)^3 - c2 rho^2, e = ce rho (c1 = lambda R T, c2 = lambda a, ce = b / 4)
   //   van der Waals      P = c1 rho / (3 - rho) - c2 rho^2       (c1 = 8 lambda T, c2 = 3 lambda)
@@ -64,7 +64,7 @@ struct RowRef {
 };
 
 template <typename R>
-hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool persist, bool regf,
+hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool persist, bool regf, bool guo,
                           int grid, hipStream_t st);
 template <typename R>
 hipError_t launch_unstream(R* fout, long long P, int nz, int nr, int bc_top, double rho_ref,

@@ -262,41 +262,62 @@ __device__ __forceinline__ R stencil_dr36(const Rings<R, W>& L, int q, const Row
   return fmad(R(8), a, -b);
 }
 
-// Post-collision populations of one node (eq. lbm with the exact-difference forcing of
-// eq. kupershtokhforcing and the source h_i of eq. axihz), in shifted storage:
-//   f*_i = f_i + omega (E_i(rho, u_b) - f_i) + E_i(rho, u_b + F/rho) - E_i(rho, u_b) + h_i,
-//   E_i(rho, v) = w_i rho (1 + Q_i(v)),  Q_i(v) = 3 c_i.v + 4.5 (c_i.v)^2 - 1.5 v.v,
-//   h_i = w_i (m0 + 3 c_i.H).
-// With g_i = f_i - w_i rho_ref and s = rho - rho_ref this is exactly
-//   g*_i = (1 - omega) g_i + w_i [omega s + m0 + rho ((omega - 1) Q_i(u_b) + Q_i(u_a)) + 3 c_i.H],
-// u_a = u_b + F/rho, and since Q_i is a quadratic form in c_i the bracket is
-//   M + 4.5 rho c_i.T.c_i + c_i.V,   M = omega s + m0 - 1.5 rho tr T,
-//   T = (omega - 1) u_b u_b + u_a u_a,  V = 3 rho ((omega - 1) u_b + u_a) + 3 H.
-// H3 = 3 H; F = (Fz, Fr).
+// Post-collision populations of one node (eq. lbm with the force of eq. kupershtokhforcing
+// and the source h_i of eq. axihz), in shifted storage g_i = f_i - w_i rho_ref,
+// s = rho - rho_ref.  With E_i(rho, v) = w_i rho (1 + Q_i(v)),
+// Q_i(v) = 3 c_i.v + 4.5 (c_i.v)^2 - 1.5 v.v, and h_i = w_i (m0 + 3 c_i.H), both force
+// applications give  g*_i = (1 - omega) g_i + w_i [M + c_i.A.c_i + c_i.V]  exactly:
+//  exact-difference method (Sec. 2.3), u_b = j/rho, u_a = u_b + F/rho:
+//   f*_i = f_i + omega (E_i(rho, u_b) - f_i) + E_i(rho, u_a) - E_i(rho, u_b) + h_i,
+//   A = 4.5 rho T, T = (omega - 1) u_b u_b + u_a u_a, M = omega s + m0 - 1.5 rho tr T,
+//   V = 3 rho (omega u_b + F/rho) + 3 H;
+//  Guo (Sec. 2.1), u = (j + F/2)/rho, p = 1 - omega/2:
+//   f*_i = f_i + omega (E_i(rho, u) - f_i) + w_i p [3 (c_i - u).F + 9 (c_i.u)(c_i.F)] + h_i,
+//   A = 4.5 omega rho u u + 4.5 p (u F + F u), M = omega s + m0 - 1.5 omega rho u.u - 3 p u.F,
+//   V = 3 (omega rho u + p F) + 3 H.
+// The bracket is assembled from M, Kz = M + A_zz, Kr = M + A_rr, Kd = M + A_zz + A_rr and
+// X = 2 A_zr.  H3 = 3 H; F = (Fz, Fr).
 template <typename R>
 __device__ __forceinline__ void collide(const R g[9], R rho, R sg, R jz, R jr, R Fz, R Fr, R m0, R H3z, R H3r,
-                                        R omega, R out[9]) {
+                                        R omega, bool guo, R out[9]) {
   const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
   const R irho = recip(rho);
-  const R ubz = jz * irho, ubr = jr * irho;
-  const R duz = Fz * irho, dur = Fr * irho;
-  const R uaz = ubz + duz, uar = ubr + dur;
-  const R om1 = omega - R(1);
-  const R tz = om1 * ubz, tr = om1 * ubr;
-  const R Tzz = fmad(tz, ubz, uaz * uaz);
-  const R Trr = fmad(tr, ubr, uar * uar);
-  const R Tzr = fmad(tz, ubr, uaz * uar);
-  const R tT = Tzz + Trr;
-  const R M = fmad(R(-1.5) * rho, tT, fmad(omega, sg, m0));
-  const R r45 = R(4.5) * rho;
-  const R Kz = fmad(r45, Tzz, M);
-  const R Kr = fmad(r45, Trr, M);
-  const R Kd = fmad(r45, tT, M);
-  const R x9 = R(9) * rho * Tzr;
-  const R Kdp = Kd + x9, Kdm = Kd - x9;
-  const R r3 = R(3) * rho;
-  const R Vz = fmad(r3, fmad(omega, ubz, duz), H3z);  // (omega - 1) u_b + u_a = omega u_b + du
-  const R Vr = fmad(r3, fmad(omega, ubr, dur), H3r);
+  R M, Kz, Kr, Kd, X, Vz, Vr;
+  if (!guo) {
+    const R ubz = jz * irho, ubr = jr * irho;
+    const R duz = Fz * irho, dur = Fr * irho;
+    const R uaz = ubz + duz, uar = ubr + dur;
+    const R om1 = omega - R(1);
+    const R tz = om1 * ubz, tr = om1 * ubr;
+    const R Tzz = fmad(tz, ubz, uaz * uaz);
+    const R Trr = fmad(tr, ubr, uar * uar);
+    const R Tzr = fmad(tz, ubr, uaz * uar);
+    const R tT = Tzz + Trr;
+    M = fmad(R(-1.5) * rho, tT, fmad(omega, sg, m0));
+    const R r45 = R(4.5) * rho;
+    Kz = fmad(r45, Tzz, M);
+    Kr = fmad(r45, Trr, M);
+    Kd = fmad(r45, tT, M);
+    X = R(9) * rho * Tzr;
+    const R r3 = R(3) * rho;
+    Vz = fmad(r3, fmad(omega, ubz, duz), H3z);  // (omega - 1) u_b + u_a = omega u_b + du
+    Vr = fmad(r3, fmad(omega, ubr, dur), H3r);
+  } else {
+    const R uz = fmad(R(0.5), Fz, jz) * irho, ur = fmad(R(0.5), Fr, jr) * irho;
+    const R orho = omega * rho, p = R(1) - R(0.5) * omega;
+    const R o45 = R(4.5) * orho, p9 = R(9) * p;
+    const R uF = fmad(uz, Fz, ur * Fr);
+    M = fmad(R(-1.5) * orho, fmad(uz, uz, ur * ur), fmad(omega, sg, m0)) - R(3) * p * uF;
+    const R Azz = fmad(o45 * uz, uz, p9 * uz * Fz);
+    const R Arr = fmad(o45 * ur, ur, p9 * ur * Fr);
+    X = fmad(R(2) * o45 * uz, ur, p9 * fmad(uz, Fr, ur * Fz));
+    Kz = M + Azz;
+    Kr = M + Arr;
+    Kd = Kz + Arr;
+    Vz = fmad(R(3), fmad(orho, uz, p * Fz), H3z);
+    Vr = fmad(R(3), fmad(orho, ur, p * Fr), H3r);
+  }
+  const R Kdp = Kd + X, Kdm = Kd - X;
   const R Sp = Vz + Vr, Sm = Vr - Vz;
   const R omc = R(1) - omega;
   out[0] = fmad(omc, g[0], w0 * M);
@@ -325,7 +346,7 @@ __device__ __forceinline__ float psi_shifted(double psi2, double psi_ref, double
 
 // REGF: carry the populations gathered in stage A for six rows in registers instead of
 // gathering them again in stage D (fewer loads that miss L2, more registers).
-template <typename R, int W, bool MOMENTS, bool REGF>
+template <typename R, int W, bool MOMENTS, bool REGF, bool GUO>
 __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem wi, char* lds, int lane) {
   const InstDev I = g.inst[wi.inst];
   const int nz = I.nz, nr = I.nr;
@@ -553,7 +574,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
           H3r = fmad(R(2) * mu36, fmad(R(-36) * ur, ir, drur), -rur * ur) * ir3;
           m0 = -rur * ir;
         }
-        collide<R>(f, rho, sg, jz, jr, fc2z, fc2r, m0, H3z, H3r, omega, o);
+        collide<R>(f, rho, sg, jz, jr, fc2z, fc2r, m0, H3z, H3r, omega, GUO && I.forcing == LBM_FORCING_GUO, o);
       }
       // Every iteration issues the same nine stores (to the sink while the stage idles or
       // for halo lanes), which lets the compiler keep the prefetched loads in flight.
@@ -595,7 +616,9 @@ struct SweepWaves {
   static constexpr int value = (PERSIST && !REGF) ? base - 1 : base;
 };
 
-template <typename R, int W, bool MOMENTS, bool PERSIST, bool REGF>
+// GUO: some instance of the launch uses Guo's forcing (a per-instance branch); otherwise
+// only the exact-difference collision is compiled in.
+template <typename R, int W, bool MOMENTS, bool PERSIST, bool REGF, bool GUO>
 __global__ void __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(SweepWaves<R, PERSIST, REGF>::value)))
 k_sweep(SweepArgs<R> g) {
   __shared__ R ring[RD][W + 4][NRING];
@@ -605,7 +628,7 @@ k_sweep(SweepArgs<R> g) {
   if (!PERSIST) {
     const int b = (int)blockIdx.x;
     const int item = g.xcd_swizzle ? xcd_map(b, (int)gridDim.x) : b;
-    if (item < g.n_items) run_item<R, W, MOMENTS, REGF>(g, g.items[item], lds, lane);
+    if (item < g.n_items) run_item<R, W, MOMENTS, REGF, GUO>(g, g.items[item], lds, lane);
     return;
   }
   for (;;) {
@@ -614,7 +637,7 @@ k_sweep(SweepArgs<R> g) {
     const int item = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform across the workgroup
     lds_barrier();
     if (item >= g.n_items) break;
-    run_item<R, W, MOMENTS, REGF>(g, g.items[item], lds, lane);
+    run_item<R, W, MOMENTS, REGF, GUO>(g, g.items[item], lds, lane);
   }
   if (lane == 0) {
     // The last workgroup out rewinds the queue for the next launch (no memset needed,
@@ -804,23 +827,29 @@ hipError_t launch_copy(const void* src, void* dst, long long bytes, int grid, hi
 
 // ---------------------------------------------------------------------------- host-side launchers
 
-template <typename R, int W, bool MOMENTS, bool PERSIST, bool REGF>
+template <typename R, int W, bool MOMENTS, bool PERSIST, bool REGF, bool GUO>
 static hipError_t launch_sweep(const SweepArgs<R>& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_sweep<R, W, MOMENTS, PERSIST, REGF>), dim3(grid), dim3(W), 0, st, g);
+  hipLaunchKernelGGL((k_sweep<R, W, MOMENTS, PERSIST, REGF, GUO>), dim3(grid), dim3(W), 0, st, g);
   return hipGetLastError();
 }
 
+template <typename R, int W, bool GUO>
+static hipError_t launch_step(const SweepArgs<R>& g, bool persist, bool regf, int grid, hipStream_t st) {
+  if (persist)
+    return regf ? launch_sweep<R, W, false, true, true, GUO>(g, grid, st)
+                : launch_sweep<R, W, false, true, false, GUO>(g, grid, st);
+  return regf ? launch_sweep<R, W, false, false, true, GUO>(g, grid, st)
+              : launch_sweep<R, W, false, false, false, GUO>(g, grid, st);
+}
+
 template <typename R>
-hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool persist, bool regf, int grid,
-                          hipStream_t st) {
-#define LBM_CASE(WW)                                                                        \
-  case WW:                                                                                  \
-    if (moments) return launch_sweep<R, WW, true, false, false>(g, grid, st);               \
-    if (persist)                                                                            \
-      return regf ? launch_sweep<R, WW, false, true, true>(g, grid, st)                     \
-                  : launch_sweep<R, WW, false, true, false>(g, grid, st);                   \
-    return regf ? launch_sweep<R, WW, false, false, true>(g, grid, st)                      \
-                : launch_sweep<R, WW, false, false, false>(g, grid, st);
+hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool persist, bool regf, bool guo,
+                          int grid, hipStream_t st) {
+#define LBM_CASE(WW)                                                                                \
+  case WW:                                                                                          \
+    if (moments) return launch_sweep<R, WW, true, false, false, false>(g, grid, st);                \
+    return guo ? launch_step<R, WW, true>(g, persist, regf, grid, st)                               \
+               : launch_step<R, WW, false>(g, persist, regf, grid, st);
   switch (width) {
     LBM_CASE(64)
     LBM_CASE(128)
@@ -832,8 +861,9 @@ hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool p
   return hipErrorInvalidValue;
 }
 
-template hipError_t sweep_dispatch<float>(const SweepArgs<float>&, int, bool, bool, bool, int, hipStream_t);
-template hipError_t sweep_dispatch<double>(const SweepArgs<double>&, int, bool, bool, bool, int, hipStream_t);
+template hipError_t sweep_dispatch<float>(const SweepArgs<float>&, int, bool, bool, bool, bool, int, hipStream_t);
+template hipError_t sweep_dispatch<double>(const SweepArgs<double>&, int, bool, bool, bool, bool, int,
+                                           hipStream_t);
 
 template <typename R>
 hipError_t launch_unstream(R* fout, long long P, int nz, int nr, int bc_top, double rho_ref, const double* rho0,

@@ -25,6 +25,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "allocation failed", -3: "HIP run
 EOS_IDEAL, EOS_VDW, EOS_CS = 0, 1, 2
 TOP_FREE_SLIP, TOP_NO_SLIP = 0, 1
 PREC_FP64, PREC_FP32 = 0, 1
+FORCING_EDM, FORCING_GUO = 0, 1
 
 # Exported names, in the order include/lbm_axi.h declares them.
 EXPORTS = [
@@ -57,6 +58,7 @@ class lbm_axi_params(ctypes.Structure):
         ("faxis_sound", ctypes.c_int32),
         ("bc_top", ctypes.c_int32),
         ("gz", ctypes.c_double),
+        ("forcing", ctypes.c_int32),
     ]
 
 
@@ -86,11 +88,12 @@ class Params:
     faxis_sound: int = 0
     bc_top: int = TOP_FREE_SLIP
     gz: float = 0.0
+    forcing: int = 0
 
     def c(self) -> lbm_axi_params:
         return lbm_axi_params(self.nz, self.nr, self.tau, self.eos, self.T, self.eos_a, self.eos_b,
                               self.eos_R, self.lam, self.A, self.axisym, self.faxis_sound,
-                              self.bc_top, self.gz)
+                              self.bc_top, self.gz, self.forcing)
 
 
 _lib = None

@@ -20,7 +20,7 @@ def cs_tc(a=1.0, b=4.0, R=1.0):
 
 def base(nz, nr, **kw):
     d = dict(nz=nz, nr=nr, tau=1.0, eos=O.EOS_CS, T=0.8 * cs_tc(), eos_a=1.0, eos_b=4.0,
-             eos_R=1.0, lam=1.0, A=0.0, axisym=1, faxis_sound=0, bc_top=0, gz=0.0)
+             eos_R=1.0, lam=1.0, A=0.0, axisym=1, faxis_sound=0, bc_top=0, gz=0.0, forcing=0)
     d.update(kw)
     return d
 

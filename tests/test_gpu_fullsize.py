@@ -21,7 +21,7 @@ LARGE_STEPS = 2
 def oparams(p):
     return O.Params(nz=p.nz, nr=p.nr, tau=p.tau, eos=p.eos, T=p.T, eos_a=p.eos_a, eos_b=p.eos_b,
                     eos_R=p.eos_R, lam=p.lam, A=p.A, axisym=p.axisym, faxis_sound=p.faxis_sound,
-                    bc_top=p.bc_top, gz=p.gz)
+                    bc_top=p.bc_top, gz=p.gz, forcing=p.forcing)
 
 
 def oracle_moments(p, rho0, steps):

@@ -98,3 +98,77 @@ def test_density_wave_against_bessel_series():
             assert np.abs(printed - rigid).max() / amp <= 1e-10
             assert err <= 0.04
             assert abs(drift) <= 1e-12
+
+
+# --------------------------------------------------------------------------- Guo vs exact difference
+
+def test_guo_forcing_against_exact_difference():
+    # The two force applications of the paper side by side (both in one batched launch):
+    # Sec. 2.1 prints Guo's term, Sec. 2.3 relies on the exact-difference method.
+    # (a) Table 1 set-up (vdW, lambda 0.01, 500 x 200, tau 1.5, R_0 = 150, T 0.8, A 0 and
+    #     -0.152, 2-D and axisymmetric): Guo's sigma = dp R / lambda lands on the printed
+    #     values (within 6 %), the exact-difference one is 1.6x them; the axisymmetric/2-D
+    #     agreement the paper reports holds for both.
+    # (b) flat-interface coexistence (150 x 100, tau 1): only the exact-difference method
+    #     with A = -0.152 sits on the Maxwell curve; Guo leaves it by tens of per cent.
+    from paper_1512_01977_amd import inputs, lbm
+    table1 = {(0.8, 0.0): (0.928, 0.928), (0.8, -0.152): (1.146, 1.158)}
+    cases = [(fo, A, ax) for fo in (0, 1) for A in (0.0, -0.152) for ax in (0, 1)]
+    ps, rhos = [], []
+    for fo, A, ax in cases:
+        p = lbm.Params(nz=500, nr=200, tau=1.5, eos=lbm.EOS_VDW, T=0.8, lam=0.01, A=A, axisym=ax, forcing=fo)
+        rv, rl, _ = lbm.lbm_axi_eos_coexistence(p)
+        ps.append(p)
+        rhos.append(inputs.droplet(500, 200, rv, rl, 150.0, zc=250.0, width=5.0, noise=1e-4, seed=1))
+    sig = {c: [] for c in cases}
+    with lbm.LbmAxi(ps, rhos) as sim:
+        sim.set_graph_chunk(100)
+        sim.step(35000)
+        for _ in range(6):
+            sim.step(5000)
+            dps = sim.laplace([250.0] * len(cases), [75.0] * len(cases), [170.0] * len(cases))
+            for k, c in enumerate(cases):
+                R = r_volume(sim.moments(k)[0], 250.0, 150.0, c[2])
+                sig[c].append(dps[k] * R / 0.01)
+        assert not sim.errors().any()
+    for fo in (0, 1):
+        for A in (0.0, -0.152):
+            s2, s3 = np.mean(sig[(fo, A, 0)]), np.mean(sig[(fo, A, 1)])
+            p2, p3 = table1[(0.8, A)]
+            print(f"forcing {'Guo' if fo else 'EDM'} A {A:+.3f}: sigma_2D {s2:.3f} (paper {p2}), "
+                  f"sigma_axis {s3:.3f} (paper {p3})", flush=True)
+            assert s3 == pytest.approx(s2, rel=0.05)
+            if fo:
+                assert s2 == pytest.approx(p2, rel=0.06) and s3 == pytest.approx(p3, rel=0.06)
+            else:
+                assert s2 > 1.5 * p2
+    coex = {}
+    cases = [(fo, A) for fo in (0, 1) for A in (0.0, -0.152)]
+    ps, rhos, mx = [], [], []
+    for fo, A in cases:
+        p = lbm.Params(nz=150, nr=100, tau=1.0, eos=lbm.EOS_VDW, T=0.8, lam=0.01, A=A, forcing=fo)
+        rv, rl, _ = lbm.lbm_axi_eos_coexistence(p)
+        ps.append(p)
+        rhos.append(inputs.slab(150, 100, rv, rl, 37.5, 112.5, width=5.0))
+        mx.append(rv)
+    with lbm.LbmAxi(ps, rhos) as sim:
+        sim.set_graph_chunk(100)
+        sim.step(20000)
+        for k, c in enumerate(cases):
+            rho = sim.moments(k)[0]
+            coex[c] = np.concatenate([rho[:, :5], rho[:, 145:]], axis=1).mean() / mx[k] - 1
+            print(f"forcing {'Guo' if c[0] else 'EDM'} A {c[1]:+.3f}: rho_v {coex[c]:+.2e} vs Maxwell", flush=True)
+    assert abs(coex[(0, -0.152)]) < 5e-3
+    assert min(abs(coex[(1, 0.0)]), abs(coex[(1, -0.152)])) > 0.1
+
+
+def r_volume(rho, zc, R0, axisym, margin=20):
+    """Equivalent radius from the liquid volume (sphere in the axisymmetric case)."""
+    nr, nz = rho.shape
+    Z, Rr = np.meshgrid(np.arange(nz) - zc, np.arange(nr) + 0.5)
+    d = np.hypot(Z, Rr)
+    rin, rout = rho[d < R0 / 2].mean(), rho[d > R0 + margin].mean()
+    frac = (rho - rout) / (rin - rout)
+    if axisym:
+        return (3 * (2 * np.pi * Rr * frac).sum() / (4 * np.pi)) ** (1 / 3)
+    return np.sqrt(2 * frac.sum() / np.pi)

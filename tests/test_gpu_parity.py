@@ -90,6 +90,8 @@ VARIANTS = {
     "vdw": dict(eos=O.EOS_VDW, lam=0.01, T=0.8, tau=0.7),
     "body_force": dict(gz=2e-6),
     "A_positive": dict(A=0.1),
+    "guo": dict(forcing=1, A=-0.152, gz=2e-6),
+    "guo_two_d_no_slip": dict(forcing=1, axisym=0, bc_top=1),
 }
 
 
@@ -175,6 +177,23 @@ def test_batch_members_equal_single_runs_bitwise():
                 one.step(60)
                 assert np.array_equal(one.get_f(), fb[k]), (prec, k)
                 assert one.mass()[0] == mb[k]
+
+
+def test_mixed_forcing_batch_equals_single_runs_bitwise():
+    # A batch with exact-difference and Guo members runs the kernel that branches per
+    # instance; every member must equal its own single run (the exact-difference one on the
+    # kernel compiled without Guo's branch).
+    L = lbm()
+    ds = [base(64, 32, A=-0.152), base(48, 30, forcing=1, A=-0.152), base(40, 24, forcing=1, axisym=0)]
+    rhos = [droplet_rho(d, 0.3 * d["nr"], eps=0.1, seed=20 + k) for k, d in enumerate(ds)]
+    for prec in (0, 1):
+        with L.LbmAxi([gpu_params(d) for d in ds], rhos, precision=prec) as bat:
+            bat.step(50)
+            fb = [bat.get_f(k) for k in range(len(ds))]
+        for k, d in enumerate(ds):
+            with L.LbmAxi(gpu_params(d), rhos[k], precision=prec) as one:
+                one.step(50)
+                assert np.array_equal(one.get_f(), fb[k]), (prec, k)
 
 
 def test_graph_replay_equals_eager_and_repeats():
