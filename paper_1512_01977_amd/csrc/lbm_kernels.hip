@@ -203,6 +203,33 @@ __device__ __forceinline__ void gather_b(const Planes<R>& pl, int nz, int nr, in
                top ? (noslip ? s0 : s0 + 2 * ps) : sp + 2 * ps);                        // 6 | 5 : 8
 }
 
+// gather_b for an interior row (0 < x < nr - 1): the same loads in the same order, without
+// the wall selects; gather() picks it for interior rows (a uniform branch).
+template <typename R>
+__device__ __forceinline__ void gather_interior(const Planes<R>& pl, int nz, int x, unsigned bm, unsigned b0,
+                                                unsigned bp, R o[9]) {
+  const unsigned row = (unsigned)sizeof(R) * (unsigned)nz, ps = pl.pstride;
+  const unsigned s0 = (unsigned)x * row, sm = s0 - row, sp = s0 + row;
+  o[0] = bload(R(0), pl.g[0], b0, s0);
+  o[1] = bload(R(0), pl.g[0], bm, s0 + ps);
+  o[3] = bload(R(0), pl.g[1], bp, s0);
+  o[2] = bload(R(0), pl.g[0], b0, sm + 2 * ps);
+  o[5] = bload(R(0), pl.g[1], bm, sm + 2 * ps);
+  o[6] = bload(R(0), pl.g[2], bp, sm);
+  o[4] = bload(R(0), pl.g[1], b0, sp + ps);
+  o[7] = bload(R(0), pl.g[2], bp, sp + ps);
+  o[8] = bload(R(0), pl.g[2], bm, sp + 2 * ps);
+}
+
+template <typename R>
+__device__ __forceinline__ void gather_row(const Planes<R>& pl, int nz, int nr, int bc_top, int x, unsigned bm,
+                                           unsigned b0, unsigned bp, R o[9]) {
+  if (x > 0 && x < nr - 1)
+    gather_interior<R>(pl, nz, x, bm, b0, bp, o);
+  else
+    gather_b<R>(pl, nz, nr, bc_top, x, bm, b0, bp, o);
+}
+
 // Equilibrium of Sec. 2.1 (c_s^2 = 1/3) relative to the storage shift:
 // E_i(rho, u) - w_i rho_ref = w_i [(rho - rho_ref) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)],
 // with sg = rho - rho_ref as summed from the shifted populations.
@@ -397,8 +424,8 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
     for (int i = 0; i < 9; ++i) fd[a][i] = R(0);
 
   R fa[9], fg[9];
-  if (a_lo < a_hi) gather_b<R>(pin, nz, nr, I.bc_top, a_lo, bm, bcol, bp, fa);
-  if (!REGF && !MOMENTS && s < e) gather_b<R>(pin, nz, nr, I.bc_top, s, bm, bcol, bp, fg);
+  if (a_lo < a_hi) gather_row<R>(pin, nz, nr, I.bc_top, a_lo, bm, bcol, bp, fa);
+  if (!REGF && !MOMENTS && s < e) gather_row<R>(pin, nz, nr, I.bc_top, s, bm, bcol, bp, fg);
   if (!MOMENTS) {  // the stores of a step, to the sink, so that loop entry looks like a loop iteration
 #pragma unroll
     for (int i = 0; i < 9; ++i) pstore(pout, i, __builtin_nondeterministic_value(R(0)), sink_lane, 0u);
@@ -435,7 +462,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
 #pragma unroll
           for (int i = 0; i < 9; ++i) fd[0][i] = f[i];
         }
-        if (x + 1 < a_hi) gather_b<R>(pin, nz, nr, I.bc_top, x + 1, bm, bcol, bp, fa);
+        if (x + 1 < a_hi) gather_row<R>(pin, nz, nr, I.bc_top, x + 1, bm, bcol, bp, fa);
         const double rd = I.rho_ref + (double)sg;  // rho in FP64 for the EOS
         double Pk, kap;
         eos_dev(I, rd, Pk, kap);
@@ -555,7 +582,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         } else {
 #pragma unroll
           for (int i = 0; i < 9; ++i) f[i] = fg[i];
-          if (x + 1 < e) gather_b<R>(pin, nz, nr, I.bc_top, x + 1, bm, bcol, bp, fg);
+          if (x + 1 < e) gather_row<R>(pin, nz, nr, I.bc_top, x + 1, bm, bcol, bp, fg);
         }
         const R sg = sg_d[6], jz = jz_d[6], jr = jr_d[6];
         const R rho = rho_ref + sg;
