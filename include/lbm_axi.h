@@ -87,7 +87,8 @@ typedef struct {
   int32_t seg_rows;     /* rows of r per work item (>= 8), 0 = whole column */
   int32_t persistent;   /* 1: persistent grid draining a work queue; 0: one workgroup per item */
   int32_t grid;         /* persistent grid size, 0 = automatic */
-  int32_t xcd_swizzle;  /* 1: neighbouring work items go to the same XCD */
+  int32_t xcd_swizzle;  /* 1: neighbouring work items go to the same XCD; 0: items longest
+                           first, dealt round-robin over the XCDs (better balance) */
   int32_t regf;         /* 1: carry gathered populations in registers (no second gather) */
 } lbm_axi_launch;
 

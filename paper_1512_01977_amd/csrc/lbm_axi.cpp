@@ -202,8 +202,10 @@ std::vector<WorkItem> build_items(const lbm_axi_s* h, const lbm_axi_launch& c, i
         items.push_back(w);
       }
   }
-  if (c.persistent) {
-    // longest first (rows swept, halo included), so the queue drains evenly
+  if (c.persistent || !c.xcd_swizzle) {
+    // longest first (rows swept, halo included), so the queue drains evenly; without the
+    // XCD swizzle the hardware deals consecutive workgroups round-robin over the XCDs, so
+    // the same order balances a one-item-per-workgroup launch too
     auto cost = [](const WorkItem& w) { return (w.e - w.s) + std::min(6, w.s) + 6; };
     std::stable_sort(items.begin(), items.end(),
                      [&](const WorkItem& a, const WorkItem& b) { return cost(a) > cost(b); });
@@ -850,8 +852,11 @@ lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch
   for (int w : widths) {
     if (w > 64 && maxnz + 12 <= w / 2) continue;  // most lanes would duplicate columns
     for (int sg : segs)
-      for (int v = 0; v < 4 && st == LBM_OK; ++v) {
-        const lbm_axi_launch c{w, sg, v & 1, 0, 1, v >> 1};
+      for (int v = 0; v < 6 && st == LBM_OK; ++v) {
+        // v: bit 0 persistent, bit 1 populations in registers; v >= 4: one item per
+        // workgroup, longest first, no XCD swizzle
+        const lbm_axi_launch c = v < 4 ? lbm_axi_launch{w, sg, v & 1, 0, 1, v >> 1}
+                                       : lbm_axi_launch{w, sg, 0, 0, 0, v & 1};
         double ms = 0.0;
         const lbm_status s = trial(c, steps_per_trial, &ms);
         if (s == LBM_ERR_HIP) st = s;
