@@ -11,13 +11,16 @@
 //                the Kupershtokh force F_K (eq. kupershtokhforcing)
 //   C (row t-4)  D_rr psi = D_r(D_r psi), D_rz psi = D_r(D_z psi), F_axis
 //                (eq. multiphasecorrections), F, physical velocity u = (j + F/2)/rho
-//   D (row t-6)  D_r u_z, D_z u_r, D_r u_r, H and h_i (eq. axihz), exact-difference
-//                forcing + BGK (eq. lbm), store the post-collision populations
+//   D (row t-6)  D_r u_z, D_z u_r, D_r u_r, H and h_i (eq. axihz), the forcing
+//                (exact difference, or Guo's term per instance) + BGK (eq. lbm),
+//                store the post-collision populations
 // Each stage's stencil input lives in a 5-row LDS ring (psi, D_z psi, D_r psi,
 // u_z, u_r); values a stage needs only at its own node travel in registers.
 // Ghost rows across the axis and the outer wall are written into the rings by the
 // producing stage with the field's mirror parity, so the stencils never branch.
-// Nothing but the populations touches HBM: one read and one write per node.
+// Nothing but the populations touches HBM: one read and one write per node.  The
+// workgroup barriers order LDS only, and each row is gathered one iteration before it
+// is used, so the loads and stores stay in flight across the pipeline steps.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -154,11 +157,6 @@ __device__ __forceinline__ float bload(float, __amdgpu_buffer_rsrc_t r, unsigned
 }
 __device__ __forceinline__ double bload(double, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-}
-
-template <typename R>
-__device__ __forceinline__ R pload(const Planes<R>& pl, int q, unsigned voff, unsigned row_off) {
-  return bload(R(0), pl.g[q / 3], voff, row_off + (unsigned)(q % 3) * pl.pstride);
 }
 
 __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
