@@ -129,7 +129,7 @@ def cpu_baseline(wl, budget_s=15.0):
     for q, f in states:
         O.step(q, f, steps)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = O.threads()
     return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{len(states)} member(s) of {wl.name} ({nodes} nodes) for {steps} steps, "
                       f"FP64 C oracle, {dt:.1f} s"}
@@ -186,6 +186,10 @@ def main():
             forms.append(run_form(w, steps, 4, 0, not args.no_tune, f"{w_name}-{p_name}"))
             del w
 
+    # practical HBM ceiling: a plain 1 GiB device-to-device copy kernel, read + write bytes
+    copy_gbps = lbm.lbm_axi_stream_copy(1 << 30, 10)
+    log(f"[bench] copy kernel: {copy_gbps:.0f} GB/s ({100 * copy_gbps / HBM_PEAK_GBPS:.1f}% of 8 TB/s)")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline: timing the oracle on a bounded sample")
@@ -193,7 +197,7 @@ def main():
         log(f"[bench] cpu baseline: {cpu['value']:.2f} MLUPS on {cpu['cores']} threads")
 
     out = {
-        "metric": "MLUPS (million lattice-node updates per second) + achieved HBM GB/s",
+        "metric": "MLUPS + achieved HBM GB/s (% of peak), FP64 plain vs FP32/batched, 1 GPU",
         "value": main_res["MLUPS"],
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -208,6 +212,7 @@ def main():
         "config": {"workload": wl.name, "nodes": wl.nodes, "instances": len(wl.params),
                    "graph_chunk": chunk, "launch": main_res["launch"]},
         "roofline": main_res["roofline"],
+        "stream_copy_GBps": copy_gbps,
         "cpu_baseline": cpu,
         "forms": [{k: f[k] for k in ("workload", "dtype", "MLUPS", "ms_per_step",
                                      "kernel_ms_per_step", "roofline", "launch")} for f in forms],

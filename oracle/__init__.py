@@ -104,6 +104,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_oracle_source.restype = None
         L.lbm_oracle_guo_source.argtypes = [ctypes.c_double] * 5 + [dp]
         L.lbm_oracle_guo_source.restype = None
+        L.lbm_oracle_threads.argtypes = []
         L.lbm_oracle_init.argtypes = [P, dp, dp, dp, dp]
         L.lbm_oracle_step.argtypes = [P, dp, ctypes.c_int64]
         L.lbm_oracle_moments.argtypes = [P, dp, dp, dp, dp]
@@ -178,6 +179,11 @@ def source(p: Params, r, rho, uz, ur, dr_uz, dz_ur, dr_ur) -> np.ndarray:
     h = np.zeros(9)
     lib().lbm_oracle_source(ctypes.byref(p.c()), r, rho, uz, ur, dr_uz, dz_ur, dr_ur, _ptr(h))
     return h
+
+
+def threads() -> int:
+    """Host threads of the oracle's parallel loops."""
+    return int(lib().lbm_oracle_threads())
 
 
 def guo_source(tau, uz, ur, Fz, Fr) -> np.ndarray:

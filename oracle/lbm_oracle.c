@@ -38,6 +38,9 @@
 #include "lbm_oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -609,4 +612,12 @@ int lbm_oracle_laplace(const lbm_oracle_params* p, const double* f, double zc, d
   if (cin == 0 || cout == 0) return ERR_ARG;
   *dp = sin_ / cin - sout / cout;
   return 0;
+}
+
+int lbm_oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

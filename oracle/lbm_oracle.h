@@ -85,6 +85,9 @@ void lbm_oracle_source(const lbm_oracle_params* p, double r, double rho, double 
  * (c_i.u)(c_i.F)/c_s^4). */
 void lbm_oracle_guo_source(double tau, double uz, double ur, double Fz, double Fr, double S[9]);
 
+/* Number of host threads the parallel loops use (OpenMP's maximum; 1 without OpenMP). */
+int lbm_oracle_threads(void);
+
 /* f = E(rho0, u_b0): post-streaming populations at t = 0.  uz0/ur0 may be NULL (0). */
 int lbm_oracle_init(const lbm_oracle_params* p, const double* rho0, const double* uz0,
                     const double* ur0, double* f);
