@@ -788,20 +788,15 @@ lbm_status lbm_axi_stream_copy(int64_t bytes, int32_t iters, double* gbps) {
   void *a = nullptr, *b = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   lbm_status st = LBM_OK;
-  int dev = 0, cus = 256;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-    cus = prop.multiProcessorCount;
   if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) st = LBM_ERR_ALLOC;
   if (st == LBM_OK && (hipMemset(a, 0, bytes) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
                        hipEventCreate(&e1) != hipSuccess))
     st = LBM_ERR_HIP;
-  const int grid = cus * 32;
-  if (st == LBM_OK && launch_copy(a, b, bytes, grid, nullptr) != hipSuccess) st = LBM_ERR_HIP;  // warm-up
+  if (st == LBM_OK && launch_copy(a, b, bytes, nullptr) != hipSuccess) st = LBM_ERR_HIP;  // warm-up
   if (st == LBM_OK) {
     (void)hipEventRecord(e0, nullptr);
     for (int i = 0; i < iters && st == LBM_OK; ++i)
-      if (launch_copy(a, b, bytes, grid, nullptr) != hipSuccess) st = LBM_ERR_HIP;
+      if (launch_copy(a, b, bytes, nullptr) != hipSuccess) st = LBM_ERR_HIP;
     (void)hipEventRecord(e1, nullptr);
     float ms = 0.f;
     if (st == LBM_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))

@@ -76,7 +76,7 @@ hipError_t launch_export(const R* fin, long long P, int nz, int nr, int bc_top, 
 template <typename R>
 hipError_t launch_rows(int K, const R* fin, long long P, const InstDev* inst, const RowRef* rows,
                        int nrows, const double* geo, double* part, hipStream_t st);
-hipError_t launch_copy(const void* src, void* dst, long long bytes, int grid, hipStream_t st);
+hipError_t launch_copy(const void* src, void* dst, long long bytes, hipStream_t st);
 hipError_t launch_finish(int K, const double* part, const int* row_start, const InstDev* inst, int n,
                          double* out, hipStream_t st);
 

@@ -653,7 +653,14 @@ k_sweep(SweepArgs<R> g) {
   if (!PERSIST) {
     const int b = (int)blockIdx.x;
     const int item = g.xcd_swizzle ? xcd_map(b, (int)gridDim.x) : b;
-    if (item < g.n_items) run_item<R, W, MOMENTS, REGF, GUO>(g, g.items[item], lds, lane);
+    if (item >= g.n_items) return;
+    const WorkItem wi = g.items[item];
+    // Only lanes 0 .. ncols + 11 (the output columns and six halo columns on either side)
+    // feed an output.  A wave with none of them ends here, which frees its SIMD slot for
+    // other workgroups (narrow members of a batch, the last strip of a row); s_barrier
+    // waits only for the waves of the group still running.
+    if (__builtin_amdgcn_readfirstlane(lane >> 6) * 64 >= wi.ncols + 12) return;
+    run_item<R, W, MOMENTS, REGF, GUO>(g, wi, lds, lane);
     return;
   }
   for (;;) {
@@ -835,17 +842,20 @@ __global__ void __launch_bounds__(256) k_finish(const double* __restrict__ part,
 
 // ---------------------------------------------------------------------------- copy (bandwidth reference)
 
-// Plain streaming copy, 16 bytes per lane per access, grid-stride.  Used to measure the
-// practical HBM copy rate and to calibrate the byte counters of the profiler.
+// Plain streaming copy: one 16-byte access per lane, one workgroup per consecutive 4 KiB, so
+// the workgroups in flight sweep a compact address window.  (Measured faster than a
+// grid-stride loop, whose workgroups drift apart.)  Used to measure the practical HBM copy
+// rate and to calibrate the byte counters of the profiler.
 __global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ src, float4* __restrict__ dst,
                                               long long n16) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n16;
-       i += (long long)gridDim.x * blockDim.x)
-    dst[i] = src[i];
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i < n16) dst[i] = src[i];
 }
 
-hipError_t launch_copy(const void* src, void* dst, long long bytes, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, st, static_cast<const float4*>(src),
+hipError_t launch_copy(const void* src, void* dst, long long bytes, hipStream_t st) {
+  const long long blocks = (bytes / 16 + 255) / 256;
+  if (blocks < 1 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<const float4*>(src),
                      static_cast<float4*>(dst), bytes / 16);
   return hipGetLastError();
 }
