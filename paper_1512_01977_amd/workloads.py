@@ -9,7 +9,9 @@ lambda = 1 with A = 0 for the moderate-ratio workloads; lambda = 0.05 with
 A = -0.152 (the paper's coexistence value) for the ensemble and where the
 liquid/vapour density ratio reaches about 1e3: with lambda = 1 (or 0.1 for the
 larger low-temperature droplets) the state leaves the real-psi range within the
-first steps from a tanh start, in the CPU oracle as well.
+first steps from a tanh start, in the CPU oracle as well.  (The flat-interface
+calibration of the coexistence module puts this EOS and scale on the Maxwell
+curve at A = -0.164; -0.152 leaves its vapour branch a few per cent high.)
 """
 from __future__ import annotations
 

@@ -110,3 +110,16 @@ def test_workspace_sizing_and_offset_limit():
     assert ws(16384, 11000, lbm.PREC_FP64)[0] == -6     # 3 * plane * 8 B >= 4 GiB
     assert ws(16384, 11000, lbm.PREC_FP32)[0] == 0
     assert ws(16384, 3, lbm.PREC_FP32)[0] == -1         # nr < 4
+
+
+def test_coexistence_zero_crossing():
+    # the A-calibration's root finder: linear interpolation between the bracketing grid
+    # points, non-finite entries (members that left the EOS domain) skipped
+    import numpy as np
+    from paper_1512_01977_amd import coexistence as C
+    assert C.zero_crossing([-0.3, -0.2, -0.1, 0.0], [0.3, 0.1, -0.1, -0.3]) == pytest.approx(-0.15)
+    assert C.zero_crossing([-0.3, -0.2, -0.1], [0.4, 0.1, -0.2]) == pytest.approx(-0.2 + 0.1 / 3)
+    assert C.zero_crossing([0.0, 1.0, 2.0], [np.nan, 1.0, -1.0]) == pytest.approx(1.5)
+    assert np.isnan(C.zero_crossing([0.0, 1.0, 2.0], [2.0, np.nan, -1.0]))  # a gap is not bridged
+    assert np.isnan(C.zero_crossing([0.0, 1.0], [1.0, 2.0]))
+    assert C.zero_crossing([0.0, 1.0], [0.0, 2.0]) == 0.0
