@@ -93,9 +93,10 @@ def run_form(wl, steps, warmup, graph_chunk, tune, label):
     return res
 
 
-def cpu_baseline(wl, budget_s=15.0):
+def cpu_baseline(wl, budget_s=15.0, max_nodes=2_000_000, threads=None):
     """The CPU oracle, as it is, on a bounded sample of the same workload: the first
-    members of the workload (or a band of rows of a single domain) for a few steps."""
+    members of the workload (or a band of rows of a single domain) for a few steps, on
+    all host threads or on the given number of them."""
     import numpy as np
 
     import oracle as O
@@ -110,26 +111,32 @@ def cpu_baseline(wl, budget_s=15.0):
     if len(wl.params) > 1:
         for p, r in zip(wl.params, wl.rho0):
             members.append((oparams(p), r))
-            if sum(q.nz * q.nr for q, _ in members) >= 2_000_000:
+            if sum(q.nz * q.nr for q, _ in members) >= max_nodes:
                 break
     else:
         p = wl.params[0]
-        rows = max(8, min(p.nr, 2_000_000 // p.nz))
+        rows = max(8, min(p.nr, max_nodes // p.nz))
         q = oparams(p)
         q.nr = rows
         members.append((q, np.ascontiguousarray(wl.rho0[0][:rows])))
     states = [(q, O.init(q, r)) for q, r in members]
     nodes = sum(q.nz * q.nr for q, _ in states)
-    t0 = time.perf_counter()
-    for q, f in states:
-        O.step(q, f, 1)
-    per_step = time.perf_counter() - t0
-    steps = max(1, int(budget_s / max(per_step, 1e-6)))
-    t0 = time.perf_counter()
-    for q, f in states:
-        O.step(q, f, steps)
-    dt = time.perf_counter() - t0
-    cores = O.threads()
+    all_threads = O.threads()
+    if threads:
+        O.set_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        for q, f in states:
+            O.step(q, f, 1)
+        per_step = time.perf_counter() - t0
+        steps = max(1, int(budget_s / max(per_step, 1e-6)))
+        t0 = time.perf_counter()
+        for q, f in states:
+            O.step(q, f, steps)
+        dt = time.perf_counter() - t0
+        cores = O.threads()
+    finally:
+        O.set_threads(all_threads)
     return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{len(states)} member(s) of {wl.name} ({nodes} nodes) for {steps} steps, "
                       f"FP64 C oracle, {dt:.1f} s"}
@@ -190,11 +197,13 @@ def main():
     copy_gbps = lbm.lbm_axi_stream_copy(1 << 30, 10)
     log(f"[bench] copy kernel: {copy_gbps:.0f} GB/s ({100 * copy_gbps / HBM_PEAK_GBPS:.1f}% of 8 TB/s)")
 
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline: timing the oracle on a bounded sample")
         cpu = cpu_baseline(wl)
         log(f"[bench] cpu baseline: {cpu['value']:.2f} MLUPS on {cpu['cores']} threads")
+        cpu1 = cpu_baseline(wl, budget_s=8.0, max_nodes=250_000, threads=1)
+        log(f"[bench] cpu baseline: {cpu1['value']:.2f} MLUPS on {cpu1['cores']} thread")
 
     out = {
         "metric": "MLUPS + achieved HBM GB/s (% of peak), FP64 plain vs FP32/batched, 1 GPU",
@@ -214,6 +223,7 @@ def main():
         "roofline": main_res["roofline"],
         "stream_copy_GBps": copy_gbps,
         "cpu_baseline": cpu,
+        "cpu_baseline_1core": cpu1,
         "forms": [{k: f[k] for k in ("workload", "dtype", "MLUPS", "ms_per_step",
                                      "kernel_ms_per_step", "roofline", "launch")} for f in forms],
         "wall_s": time.perf_counter() - t_all,

@@ -105,6 +105,8 @@ def lib() -> ctypes.CDLL:
         L.lbm_oracle_guo_source.argtypes = [ctypes.c_double] * 5 + [dp]
         L.lbm_oracle_guo_source.restype = None
         L.lbm_oracle_threads.argtypes = []
+        L.lbm_oracle_set_threads.argtypes = [ctypes.c_int]
+        L.lbm_oracle_set_threads.restype = None
         L.lbm_oracle_init.argtypes = [P, dp, dp, dp, dp]
         L.lbm_oracle_step.argtypes = [P, dp, ctypes.c_int64]
         L.lbm_oracle_moments.argtypes = [P, dp, dp, dp, dp]
@@ -184,6 +186,11 @@ def source(p: Params, r, rho, uz, ur, dr_uz, dz_ur, dr_ur) -> np.ndarray:
 def threads() -> int:
     """Host threads of the oracle's parallel loops."""
     return int(lib().lbm_oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Host threads for the oracle's parallel loops from now on."""
+    lib().lbm_oracle_set_threads(int(n))
 
 
 def guo_source(tau, uz, ur, Fz, Fr) -> np.ndarray:

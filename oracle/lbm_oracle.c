@@ -621,3 +621,11 @@ int lbm_oracle_threads(void) {
   return 1;
 #endif
 }
+
+void lbm_oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

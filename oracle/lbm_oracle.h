@@ -88,6 +88,10 @@ void lbm_oracle_guo_source(double tau, double uz, double ur, double Fz, double F
 /* Number of host threads the parallel loops use (OpenMP's maximum; 1 without OpenMP). */
 int lbm_oracle_threads(void);
 
+/* Set the number of host threads for the parallel loops that follow (n >= 1; ignored
+ * without OpenMP).  Used to time the oracle on one core. */
+void lbm_oracle_set_threads(int n);
+
 /* f = E(rho0, u_b0): post-streaming populations at t = 0.  uz0/ur0 may be NULL (0). */
 int lbm_oracle_init(const lbm_oracle_params* p, const double* rho0, const double* uz0,
                     const double* ur0, double* f);

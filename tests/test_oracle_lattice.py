@@ -238,3 +238,23 @@ def test_source_moments_recover_axisymmetric_terms(printed):
         assert (CZ * h).sum() == pytest.approx(Cz - rho * uz * ur / r, rel=1e-11, abs=1e-18)
         ok &= abs((CR * h).sum() - (Cr - rho * ur * ur / r)) <= 1e-11 * abs(Cr) + 1e-18
     assert ok == (printed == 0)
+
+
+def test_oracle_thread_count_does_not_change_results():
+    # the one-core timing of the benchmark sets the oracle's thread count: results are the
+    # same bits on one thread as on all of them (each node is written by one iteration)
+    import numpy as np
+    from cases import base, droplet_rho, oracle_params
+    d = base(32, 16, tau=0.9)
+    p = oracle_params(d)
+    rho0 = droplet_rho(d, 8.0, zc=16.0)
+    n_all = O.threads()
+    f_all = O.step(p, O.init(p, rho0), 20)
+    O.set_threads(1)
+    try:
+        assert O.threads() == 1
+        f_one = O.step(p, O.init(p, rho0), 20)
+    finally:
+        O.set_threads(n_all)
+    assert O.threads() == n_all
+    assert np.array_equal(f_all, f_one)
