@@ -83,7 +83,8 @@ typedef struct {
 
 /* Launch shape of the fused step kernel (chosen by lbm_axi_autotune or set by hand). */
 typedef struct {
-  int32_t width;        /* lanes per workgroup along z: 64, 128 or 256 (12 are halo) */
+  int32_t width;        /* lanes per workgroup along z: 64, 128 or 256; a workgroup writes the
+                           whole 128-byte lines that fit in width - 12 columns (12 are halo) */
   int32_t seg_rows;     /* rows of r per work item (>= 8), 0 = whole column */
   int32_t persistent;   /* 1: persistent grid draining a work queue; 0: one workgroup per item */
   int32_t grid;         /* persistent grid size, 0 = automatic */

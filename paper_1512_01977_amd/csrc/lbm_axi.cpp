@@ -105,13 +105,14 @@ double reference_density(const lbm_axi_params& p, const double* rho0) {
   return s[s.size() / 2];
 }
 
-InstDev make_inst(const lbm_axi_params& p, long long base, double rho_ref) {
+InstDev make_inst(const lbm_axi_params& p, long long base, double rho_ref, int esize) {
   InstDev d{};
   d.rho_ref = rho_ref;
   d.psi_ref = rho_ref > 0.0 ? eos_psi(p, rho_ref) : 0.0;
   d.base = base;
   d.nz = p.nz;
   d.nr = p.nr;
+  d.pitch = row_pitch(p.nz, esize);
   d.eos = p.eos;
   d.axisym = p.axisym;
   d.faxis_sound = p.faxis_sound;
@@ -147,7 +148,7 @@ void shape_cost(const lbm_axi_s* h, int width, int seg, long long* items, long l
   *items = 0;
   *lane_iters = 0;
   *longest = 0;
-  const int wout = width - 12;
+  const int wout = strip_cols(width, h->esize);
   for (const auto& p : h->prm) {
     const int sg = seg > 0 ? std::min(seg, p.nr) : p.nr;
     const long long nstrip = std::max(1, (p.nz + wout - 1) / wout);
@@ -182,10 +183,11 @@ lbm_axi_launch default_launch(const lbm_axi_s* h) {
   return best;
 }
 
-// Strips of width - 12 output columns times row segments, for every instance.
+// Strips of whole 128-byte lines of output columns (at most width - 12) times row
+// segments, for every instance.
 std::vector<WorkItem> build_items(const lbm_axi_s* h, const lbm_axi_launch& c, int only_inst) {
   std::vector<WorkItem> items;
-  const int wout = c.width - 12;
+  const int wout = strip_cols(c.width, h->esize);
   for (int k = 0; k < h->n; ++k) {
     if (only_inst >= 0 && k != only_inst) continue;
     const auto& p = h->prm[k];
@@ -338,9 +340,10 @@ bool offsets_fit(long long plane, int esize) { return 3.0 * (double)plane * (dou
 size_t f_bytes_of(int n, const lbm_axi_params* params, int prec, long long* plane_out,
                   std::vector<long long>* bases) {
   long long off = 0;
+  const int esize = prec == LBM_PREC_FP32 ? 4 : 8;
   for (int k = 0; k < n; ++k) {
     if (bases) bases->push_back(off);
-    const long long nn = (long long)params[k].nz * params[k].nr;
+    const long long nn = (long long)row_pitch(params[k].nz, esize) * params[k].nr;
     off += (nn + 63) / 64 * 64;  // every instance starts on a 256-byte boundary
   }
   // A tail of kSinkElems per plane past the last instance: the step kernel's halo lanes
@@ -369,7 +372,8 @@ hipError_t unstream_into(lbm_axi_s* h, int k, const double* rho0, const double* 
                          const double* f0) {
   const auto& p = h->prm[k];
   R* dst = static_cast<R*>(h->fbuf[h->cur]) + h->base[k];
-  return launch_unstream<R>(dst, h->plane, p.nz, p.nr, p.bc_top, h->hinst[k].rho_ref, rho0, uz0, ur0, f0,
+  return launch_unstream<R>(dst, h->plane, p.nz, h->hinst[k].pitch, p.nr, p.bc_top, h->hinst[k].rho_ref, rho0,
+                            uz0, ur0, f0,
                             h->stream);
 }
 
@@ -441,7 +445,7 @@ lbm_status create(int n, const lbm_axi_params* params, int prec, const double* c
   }
   for (int k = 0; k < n; ++k) {
     const double rref = prec == LBM_PREC_FP32 ? reference_density(params[k], rho0[k]) : 0.0;
-    h->hinst.push_back(make_inst(params[k], h->base[k], rref));
+    h->hinst.push_back(make_inst(params[k], h->base[k], rref, h->esize));
     h->nodes += (long long)params[k].nz * params[k].nr;
     h->any_guo = h->any_guo || params[k].forcing == LBM_FORCING_GUO;
   }
@@ -739,10 +743,10 @@ lbm_status lbm_axi_get_f(lbm_axi_t h, int32_t k, double* f) {
   HIPCHK(hipMalloc(&tmp, 9 * n * sizeof(double)));
   hipError_t e =
       h->prec == LBM_PREC_FP32
-          ? launch_export<float>(static_cast<const float*>(h->fbuf[h->cur]) + h->base[k], h->plane, p.nz, p.nr,
-                                 p.bc_top, h->hinst[k].rho_ref, tmp, h->stream)
+          ? launch_export<float>(static_cast<const float*>(h->fbuf[h->cur]) + h->base[k], h->plane, p.nz,
+                                 h->hinst[k].pitch, p.nr, p.bc_top, h->hinst[k].rho_ref, tmp, h->stream)
           : launch_export<double>(static_cast<const double*>(h->fbuf[h->cur]) + h->base[k], h->plane, p.nz,
-                                  p.nr, p.bc_top, h->hinst[k].rho_ref, tmp, h->stream);
+                                  h->hinst[k].pitch, p.nr, p.bc_top, h->hinst[k].rho_ref, tmp, h->stream);
   lbm_status st = LBM_OK;
   if (e != hipSuccess ||
       hipMemcpyAsync(f, tmp, 9 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||

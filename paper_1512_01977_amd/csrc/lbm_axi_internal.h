@@ -17,6 +17,7 @@ double eos_psi(const lbm_axi_params& p, double rho);  // sqrt(rho/3 - P_k), 0 fo
 struct InstDev {
   long long base;    // index of node (0, 0) of the instance inside every distribution plane
   int nz, nr;
+  int pitch;         // elements from one row of a plane to the next (nz rounded up to 128 bytes)
   int eos, axisym, faxis_sound, bc_top, forcing;
   // EOS in the form the kernels evaluate (FP64 in every precision):
   //   Carnahan-Starling  P = c1 rho n(e) / (1 - e)^3 - c2 rho^2, e = ce rho (c1 = lambda R T, c2 = lambda a, ce = b / 4)
@@ -36,6 +37,16 @@ struct InstDev {
 struct WorkItem {
   int inst, k0, ncols, s, e;
 };
+
+// Rows of the distribution planes start on 128-byte boundaries and the step kernel's strips
+// of output columns are whole 128-byte lines, so that no line is written in part by two
+// workgroups (HBM has no byte masks: a partly written line costs a read-modify-write).
+inline int line_elems(int esize) { return 128 / esize; }
+inline int row_pitch(int nz, int esize) { return (nz + line_elems(esize) - 1) / line_elems(esize) * line_elems(esize); }
+inline int strip_cols(int width, int esize) {
+  // output columns of a workgroup of `width` lanes: six halo lanes on either side
+  return (width - 12) / line_elems(esize) * line_elems(esize);
+}
 
 // Elements at the end of every distribution plane that belong to no instance (a sink for
 // the stores of the step kernel's halo lanes); at least the widest workgroup.
@@ -67,11 +78,11 @@ template <typename R>
 hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool persist, bool regf, bool guo,
                           int grid, hipStream_t st);
 template <typename R>
-hipError_t launch_unstream(R* fout, long long P, int nz, int nr, int bc_top, double rho_ref,
+hipError_t launch_unstream(R* fout, long long P, int nz, int pitch, int nr, int bc_top, double rho_ref,
                            const double* rho0,
                            const double* uz0, const double* ur0, const double* f0, hipStream_t st);
 template <typename R>
-hipError_t launch_export(const R* fin, long long P, int nz, int nr, int bc_top, double rho_ref,
+hipError_t launch_export(const R* fin, long long P, int nz, int pitch, int nr, int bc_top, double rho_ref,
                          double* out, hipStream_t st);
 template <typename R>
 hipError_t launch_rows(int K, const R* fin, long long P, const InstDev* inst, const RowRef* rows,

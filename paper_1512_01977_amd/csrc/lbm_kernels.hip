@@ -1,9 +1,9 @@
 // HIP kernels of the axisymmetric multiphase lattice Boltzmann step (arXiv:1512.01977)
 // for gfx950.  See lbm_axi.h for conventions.
 //
-// Fused step kernel ("sweep").  One workgroup of W lanes owns a strip of W - 12
-// output columns (z, contiguous in memory) plus a 6-column halo on each side,
-// and walks up the rows (r) of one segment.  Every iteration t advances four
+// Fused step kernel ("sweep").  One workgroup of W lanes owns a strip of output
+// columns (z, contiguous in memory; whole 128-byte lines, at most W - 12 columns)
+// plus a 6-column halo on each side, and walks up the rows (r) of one segment.  Every iteration t advances four
 // pipeline stages that lag each other by two rows:
 //   A (row t)    pull-gather the 9 populations with the wall maps, moments rho and
 //                j, EOS in FP64: P_k, kappa = dP_k/drho, psi = sqrt(rho/3 - P_k)
@@ -99,11 +99,11 @@ __device__ __forceinline__ void eos_dev(const InstDev& I, double rho, double& P,
 // cm, c0, cp are the wrapped columns k-1, k, k+1.  Row pointers are uniform across the
 // workgroup and the lane offsets are 32-bit, so the loads take a scalar base.
 template <typename R>
-__device__ __forceinline__ void gather(const R* __restrict__ f, long long P, int nz, int nr, int bc_top,
+__device__ __forceinline__ void gather(const R* __restrict__ f, long long P, int pitch, int nr, int bc_top,
                                        int x, unsigned cm, unsigned c0, unsigned cp, R o[9]) {
-  const R* r0 = f + (long long)x * nz;
-  const R* rm = x > 0 ? r0 - nz : r0;       // row x-1 feeds the directions with c_r = +1
-  const R* rp = x < nr - 1 ? r0 + nz : r0;  // row x+1 feeds the directions with c_r = -1
+  const R* r0 = f + (long long)x * pitch;
+  const R* rm = x > 0 ? r0 - pitch : r0;       // row x-1 feeds the directions with c_r = +1
+  const R* rp = x < nr - 1 ? r0 + pitch : r0;  // row x+1 feeds the directions with c_r = -1
   o[0] = r0[c0];
   o[1] = (r0 + P)[cm];
   o[3] = (r0 + 3 * P)[cp];
@@ -177,9 +177,9 @@ __device__ __forceinline__ void pstore(const Planes<R>& pl, int q, R v, unsigned
 // column), so that the nine loads form one straight sequence: the compiler can then
 // track them individually and overlap them with the stores still in flight.
 template <typename R>
-__device__ __forceinline__ void gather_b(const Planes<R>& pl, int nz, int nr, int bc_top, int x, unsigned bm,
+__device__ __forceinline__ void gather_b(const Planes<R>& pl, int pitch, int nr, int bc_top, int x, unsigned bm,
                                          unsigned b0, unsigned bp, R o[9]) {
-  const unsigned row = (unsigned)sizeof(R) * (unsigned)nz, ps = pl.pstride;
+  const unsigned row = (unsigned)sizeof(R) * (unsigned)pitch, ps = pl.pstride;
   const unsigned s0 = (unsigned)x * row;
   const bool axis = x == 0, top = x == nr - 1;
   const bool noslip = top && bc_top == LBM_TOP_NO_SLIP;
@@ -204,9 +204,9 @@ __device__ __forceinline__ void gather_b(const Planes<R>& pl, int nz, int nr, in
 // gather_b for an interior row (0 < x < nr - 1): the same loads in the same order, without
 // the wall selects; gather() picks it for interior rows (a uniform branch).
 template <typename R>
-__device__ __forceinline__ void gather_interior(const Planes<R>& pl, int nz, int x, unsigned bm, unsigned b0,
+__device__ __forceinline__ void gather_interior(const Planes<R>& pl, int pitch, int x, unsigned bm, unsigned b0,
                                                 unsigned bp, R o[9]) {
-  const unsigned row = (unsigned)sizeof(R) * (unsigned)nz, ps = pl.pstride;
+  const unsigned row = (unsigned)sizeof(R) * (unsigned)pitch, ps = pl.pstride;
   const unsigned s0 = (unsigned)x * row, sm = s0 - row, sp = s0 + row;
   o[0] = bload(R(0), pl.g[0], b0, s0);
   o[1] = bload(R(0), pl.g[0], bm, s0 + ps);
@@ -220,12 +220,12 @@ __device__ __forceinline__ void gather_interior(const Planes<R>& pl, int nz, int
 }
 
 template <typename R>
-__device__ __forceinline__ void gather_row(const Planes<R>& pl, int nz, int nr, int bc_top, int x, unsigned bm,
+__device__ __forceinline__ void gather_row(const Planes<R>& pl, int pitch, int nr, int bc_top, int x, unsigned bm,
                                            unsigned b0, unsigned bp, R o[9]) {
   if (x > 0 && x < nr - 1)
-    gather_interior<R>(pl, nz, x, bm, b0, bp, o);
+    gather_interior<R>(pl, pitch, x, bm, b0, bp, o);
   else
-    gather_b<R>(pl, nz, nr, bc_top, x, bm, b0, bp, o);
+    gather_b<R>(pl, pitch, nr, bc_top, x, bm, b0, bp, o);
 }
 
 // Equilibrium of Sec. 2.1 (c_s^2 = 1/3) relative to the storage shift:
@@ -381,8 +381,13 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
   const Planes<R> pin = make_planes<R>(g.fin + I.base, g.plane);
   const Planes<R> pout = make_planes<R>(g.fout + I.base, g.plane);
   const unsigned bcol = col * (unsigned)sizeof(R), bm = cm * (unsigned)sizeof(R), bp = cp * (unsigned)sizeof(R);
-  // Halo lanes store into the plane's sink (past every instance, one slot per lane) rather
-  // than skipping the stores, so every wave issues the same store sequence.
+  // The strip that ends a row also fills the row's padding (columns nz .. pitch - 1, never
+  // read) from its first halo lanes, so that the row's last line is written whole.
+  const int ucol = wi.k0 - 6 + lane;
+  const bool pad_lane = wi.k0 + wi.ncols == nz && ucol >= nz && ucol < I.pitch;
+  const unsigned bstore = pad_lane ? (unsigned)ucol * (unsigned)sizeof(R) : bcol;
+  // Other halo lanes store into the plane's sink (past every instance, one slot per lane)
+  // rather than skipping the stores, so every wave issues the same store sequence.
   const unsigned sink_lane = (unsigned)((g.sink - I.base) * (long long)sizeof(R)) + (unsigned)lane * (unsigned)sizeof(R);
   const int s = wi.s, e = wi.e;
   const int a_lo = max(0, s - 6), a_hi = min(nr, e + 6);
@@ -422,8 +427,8 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
     for (int i = 0; i < 9; ++i) fd[a][i] = R(0);
 
   R fa[9], fg[9];
-  if (a_lo < a_hi) gather_row<R>(pin, nz, nr, I.bc_top, a_lo, bm, bcol, bp, fa);
-  if (!REGF && !MOMENTS && s < e) gather_row<R>(pin, nz, nr, I.bc_top, s, bm, bcol, bp, fg);
+  if (a_lo < a_hi) gather_row<R>(pin, I.pitch, nr, I.bc_top, a_lo, bm, bcol, bp, fa);
+  if (!REGF && !MOMENTS && s < e) gather_row<R>(pin, I.pitch, nr, I.bc_top, s, bm, bcol, bp, fg);
   if (!MOMENTS) {  // the stores of a step, to the sink, so that loop entry looks like a loop iteration
 #pragma unroll
     for (int i = 0; i < 9; ++i) pstore(pout, i, __builtin_nondeterministic_value(R(0)), sink_lane, 0u);
@@ -460,7 +465,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
 #pragma unroll
           for (int i = 0; i < 9; ++i) fd[0][i] = f[i];
         }
-        if (x + 1 < a_hi) gather_row<R>(pin, nz, nr, I.bc_top, x + 1, bm, bcol, bp, fa);
+        if (x + 1 < a_hi) gather_row<R>(pin, I.pitch, nr, I.bc_top, x + 1, bm, bcol, bp, fa);
         const double rd = I.rho_ref + (double)sg;  // rho in FP64 for the EOS
         double Pk, kap;
         eos_dev(I, rd, Pk, kap);
@@ -580,7 +585,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         } else {
 #pragma unroll
           for (int i = 0; i < 9; ++i) f[i] = fg[i];
-          if (x + 1 < e) gather_row<R>(pin, nz, nr, I.bc_top, x + 1, bm, bcol, bp, fg);
+          if (x + 1 < e) gather_row<R>(pin, I.pitch, nr, I.bc_top, x + 1, bm, bcol, bp, fg);
         }
         const R sg = sg_d[6], jz = jz_d[6], jr = jr_d[6];
         const R rho = rho_ref + sg;
@@ -603,8 +608,8 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
       }
       // Every iteration issues the same nine stores (to the sink while the stage idles or
       // for halo lanes), which lets the compiler keep the prefetched loads in flight.
-      const unsigned orow = active ? (unsigned)x * (unsigned)sizeof(R) * (unsigned)nz : 0u;
-      const unsigned voff = active && out_lane ? bcol : sink_lane - orow;
+      const unsigned orow = active ? (unsigned)x * (unsigned)sizeof(R) * (unsigned)I.pitch : 0u;
+      const unsigned voff = active && (out_lane || pad_lane) ? bstore : sink_lane - orow;
 #pragma unroll
       for (int i = 0; i < 9; ++i) pstore(pout, i, o[i], voff, orow);
     }
@@ -656,10 +661,13 @@ k_sweep(SweepArgs<R> g) {
     if (item >= g.n_items) return;
     const WorkItem wi = g.items[item];
     // Only lanes 0 .. ncols + 11 (the output columns and six halo columns on either side)
-    // feed an output.  A wave with none of them ends here, which frees its SIMD slot for
-    // other workgroups (narrow members of a batch, the last strip of a row); s_barrier
-    // waits only for the waves of the group still running.
-    if (__builtin_amdgcn_readfirstlane(lane >> 6) * 64 >= wi.ncols + 12) return;
+    // feed an output, and at the end of a row the lanes that fill its padding store.  A wave
+    // with none of them ends here, which frees its SIMD slot for other workgroups (narrow
+    // members of a batch, the last strip of a row); s_barrier waits only for the waves of
+    // the group still running.
+    const InstDev* ip = g.inst + wi.inst;
+    const int need = wi.k0 + wi.ncols == ip->nz ? max(wi.ncols + 12, ip->pitch - wi.k0 + 6) : wi.ncols + 12;
+    if (__builtin_amdgcn_readfirstlane(lane >> 6) * 64 >= need) return;
     run_item<R, W, MOMENTS, REGF, GUO>(g, wi, lds, lane);
     return;
   }
@@ -693,7 +701,7 @@ __device__ __constant__ int c_opposite[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};  // c -
 // the inverse of the pull map.  f0 is either a double [9][nr][nz] array, or (when
 // f0 == nullptr) the equilibrium E(rho0, u0) of the initial fields (Sec. 2.1).
 template <typename R>
-__global__ void k_unstream(R* __restrict__ fout, long long P, int nz, int nr, int bc_top, double rho_ref,
+__global__ void k_unstream(R* __restrict__ fout, long long P, int nz, int pitch, int nr, int bc_top, double rho_ref,
                            const double* __restrict__ rho0, const double* __restrict__ uz0,
                            const double* __restrict__ ur0, const double* __restrict__ f0) {
   const double wgt[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
@@ -727,14 +735,14 @@ __global__ void k_unstream(R* __restrict__ fout, long long P, int nz, int nr, in
                                     ur0 ? ur0[tn] : 0.0, e);
         v = e[ti];
       }
-      fout[i * P + id] = R(v);
+      fout[i * P + (long long)j * pitch + k] = R(v);
     }
   }
 }
 
 template <typename R>
-__global__ void k_export(const R* __restrict__ fin, long long P, int nz, int nr, int bc_top, double rho_ref,
-                         double* __restrict__ out) {
+__global__ void k_export(const R* __restrict__ fin, long long P, int nz, int pitch, int nr, int bc_top,
+                         double rho_ref, double* __restrict__ out) {
   const double wgt[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
                          1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
   const long long n = (long long)nz * nr;
@@ -742,7 +750,7 @@ __global__ void k_export(const R* __restrict__ fin, long long P, int nz, int nr,
        id += (long long)gridDim.x * blockDim.x) {
     const int k = (int)(id % nz), j = (int)(id / nz);
     R f[9];
-    gather<R>(fin, P, nz, nr, bc_top, j, (unsigned)wrapi(k - 1, nz), (unsigned)k, (unsigned)wrapi(k + 1, nz), f);
+    gather<R>(fin, P, pitch, nr, bc_top, j, (unsigned)wrapi(k - 1, nz), (unsigned)k, (unsigned)wrapi(k + 1, nz), f);
     for (int i = 0; i < 9; ++i) out[i * n + id] = (double)f[i] + wgt[i] * rho_ref;
   }
 }
@@ -786,7 +794,7 @@ __global__ void __launch_bounds__(256) k_rows(const R* __restrict__ fin, long lo
   const double rj = j + 0.5;
   for (int k = threadIdx.x; k < nz; k += 256) {
     R o[9];
-    gather<R>(f, P, nz, I.nr, I.bc_top, j, (unsigned)wrapi(k - 1, nz), (unsigned)k, (unsigned)wrapi(k + 1, nz), o);
+    gather<R>(f, P, I.pitch, I.nr, I.bc_top, j, (unsigned)wrapi(k - 1, nz), (unsigned)k, (unsigned)wrapi(k + 1, nz), o);
     const R sg = o[0] + o[1] + o[2] + o[3] + o[4] + o[5] + o[6] + o[7] + o[8];
     const double rho = I.rho_ref + (double)sg;
     if (K == 1) {
@@ -901,29 +909,31 @@ template hipError_t sweep_dispatch<double>(const SweepArgs<double>&, int, bool, 
                                            hipStream_t);
 
 template <typename R>
-hipError_t launch_unstream(R* fout, long long P, int nz, int nr, int bc_top, double rho_ref, const double* rho0,
-                           const double* uz0, const double* ur0, const double* f0, hipStream_t st) {
+hipError_t launch_unstream(R* fout, long long P, int nz, int pitch, int nr, int bc_top, double rho_ref,
+                           const double* rho0, const double* uz0, const double* ur0, const double* f0,
+                           hipStream_t st) {
   const long long n = (long long)nz * nr;
   const int grid = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
-  hipLaunchKernelGGL((k_unstream<R>), dim3(grid), dim3(256), 0, st, fout, P, nz, nr, bc_top, rho_ref, rho0,
-                     uz0, ur0, f0);
+  hipLaunchKernelGGL((k_unstream<R>), dim3(grid), dim3(256), 0, st, fout, P, nz, pitch, nr, bc_top, rho_ref,
+                     rho0, uz0, ur0, f0);
   return hipGetLastError();
 }
-template hipError_t launch_unstream<float>(float*, long long, int, int, int, double, const double*,
+template hipError_t launch_unstream<float>(float*, long long, int, int, int, int, double, const double*,
                                            const double*, const double*, const double*, hipStream_t);
-template hipError_t launch_unstream<double>(double*, long long, int, int, int, double, const double*,
+template hipError_t launch_unstream<double>(double*, long long, int, int, int, int, double, const double*,
                                             const double*, const double*, const double*, hipStream_t);
 
 template <typename R>
-hipError_t launch_export(const R* fin, long long P, int nz, int nr, int bc_top, double rho_ref, double* out,
-                         hipStream_t st) {
+hipError_t launch_export(const R* fin, long long P, int nz, int pitch, int nr, int bc_top, double rho_ref,
+                         double* out, hipStream_t st) {
   const long long n = (long long)nz * nr;
   const int grid = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
-  hipLaunchKernelGGL((k_export<R>), dim3(grid), dim3(256), 0, st, fin, P, nz, nr, bc_top, rho_ref, out);
+  hipLaunchKernelGGL((k_export<R>), dim3(grid), dim3(256), 0, st, fin, P, nz, pitch, nr, bc_top, rho_ref, out);
   return hipGetLastError();
 }
-template hipError_t launch_export<float>(const float*, long long, int, int, int, double, double*, hipStream_t);
-template hipError_t launch_export<double>(const double*, long long, int, int, int, double, double*,
+template hipError_t launch_export<float>(const float*, long long, int, int, int, int, double, double*,
+                                         hipStream_t);
+template hipError_t launch_export<double>(const double*, long long, int, int, int, int, double, double*,
                                           hipStream_t);
 
 template <typename R>

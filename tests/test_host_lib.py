@@ -92,8 +92,9 @@ def test_tuning_size_class_keys():
 
 
 def test_workspace_sizing_and_offset_limit():
-    # Two buffers of nine planes, each plane padded per instance to 64 elements plus a
-    # 256-element sink; layouts whose three planes would span 4 GiB are refused up front.
+    # Two buffers of nine planes; rows padded to 128 bytes, each instance to 64 elements,
+    # plus a 256-element sink per plane; layouts whose three planes would span 4 GiB are
+    # refused up front.
     import ctypes
     from paper_1512_01977_amd import lbm
     L = lbm.lib()
@@ -105,8 +106,10 @@ def test_workspace_sizing_and_offset_limit():
 
     st, nb = ws(16384, 8192, lbm.PREC_FP64)
     assert st == 0 and nb == 2 * 9 * 8 * (16384 * 8192 + 256)
-    st, nb = ws(100, 7, lbm.PREC_FP32)
-    assert st == 0 and nb == 2 * 9 * 4 * (704 + 256)
+    st, nb = ws(100, 7, lbm.PREC_FP32)                  # rows of 128 floats
+    assert st == 0 and nb == 2 * 9 * 4 * (896 + 256)
+    st, nb = ws(100, 7, lbm.PREC_FP64)                  # rows of 112 doubles
+    assert st == 0 and nb == 2 * 9 * 8 * (832 + 256)
     assert ws(16384, 11000, lbm.PREC_FP64)[0] == -6     # 3 * plane * 8 B >= 4 GiB
     assert ws(16384, 11000, lbm.PREC_FP32)[0] == 0
     assert ws(16384, 3, lbm.PREC_FP32)[0] == -1         # nr < 4
