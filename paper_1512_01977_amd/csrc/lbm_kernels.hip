@@ -375,7 +375,9 @@ template <typename R, int W, bool MOMENTS, bool REGF, bool GUO>
 __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem wi, char* lds, int lane) {
   const InstDev I = g.inst[wi.inst];
   const int nz = I.nz, nr = I.nr;
-  const unsigned col = (unsigned)wrapi(wi.k0 - 6 + lane, nz);
+  // lanes past the right halo feed nothing: they gather the last halo lane's column (the
+  // same lines), so they add no memory traffic
+  const unsigned col = (unsigned)wrapi(wi.k0 - 6 + min(lane, wi.ncols + 11), nz);
   const unsigned cm = (unsigned)wrapi((int)col - 1, nz), cp = (unsigned)wrapi((int)col + 1, nz);
   const bool out_lane = lane >= 6 && lane < 6 + wi.ncols;
   const Planes<R> pin = make_planes<R>(g.fin + I.base, g.plane);
