@@ -120,8 +120,9 @@ lbm_status lbm_axi_eos_coexistence(const lbm_axi_params* p, double* rho_v, doubl
  * Errors: LBM_ERR_ARG (NULL out/rho0, nz < 1, nr < 4, nz*nr > 2^31, tau <= 1/2, unknown
  * eos/bc/forcing/flag, non-finite A, gz or T, CS b <= 0, lambda <= 0 for a non-ideal EOS);
  * LBM_ERR_NONFINITE / LBM_ERR_EOS_DOMAIN (rho0 non-finite, <= 0, or psi not real);
- * LBM_ERR_UNSUPPORTED (three direction planes would span 4 GiB or more: the step kernel
- * addresses them with 32-bit offsets); LBM_ERR_ALLOC; LBM_ERR_HIP.  *out is NULL on error. */
+ * LBM_ERR_UNSUPPORTED (rows so wide that 22 of them, nine planes each, span 2 GiB or more,
+ * about nz > 1.4e6 in FP64: the step kernel addresses the rows of a work item with 32-bit
+ * offsets); LBM_ERR_ALLOC; LBM_ERR_HIP.  *out is NULL on error. */
 lbm_status lbm_axi_init(const lbm_axi_params* p, int32_t precision, const double* rho0,
                         const double* uz0, const double* ur0, void* stream, lbm_axi_t* out);
 
@@ -133,7 +134,8 @@ lbm_status lbm_axi_batch_init(int32_t n, const lbm_axi_params* params, int32_t p
 
 /* Device bytes needed for the two distribution buffers of an n-instance batch (host
  * arithmetic only).  Errors: LBM_ERR_ARG (as lbm_axi_batch_init's parameter checks),
- * LBM_ERR_UNSUPPORTED (the layout exceeds the 32-bit plane offsets; nothing to allocate). */
+ * LBM_ERR_UNSUPPORTED (rows too wide for the step kernel's 32-bit offsets, as for
+ * lbm_axi_init; nothing to allocate). */
 lbm_status lbm_axi_workspace_bytes(int32_t n, const lbm_axi_params* params, int32_t precision,
                                    size_t* bytes);
 

@@ -19,7 +19,7 @@ struct lbm_axi_s {
   std::vector<lbm_axi_params> prm;
   std::vector<InstDev> hinst;
   std::vector<long long> base;
-  long long plane = 0;  // elements per direction plane (all instances, padded)
+  long long felems = 0;  // elements of one distribution buffer (all instances, padded)
   long long nodes = 0;  // real nodes
   size_t esize = 8;
   hipStream_t stream = nullptr;
@@ -150,7 +150,7 @@ void shape_cost(const lbm_axi_s* h, int width, int seg, long long* items, long l
   *longest = 0;
   const int wout = strip_cols(width, h->esize);
   for (const auto& p : h->prm) {
-    const int sg = seg > 0 ? std::min(seg, p.nr) : p.nr;
+    const int sg = std::min(seg > 0 ? std::min(seg, p.nr) : p.nr, max_item_rows(row_pitch(p.nz, h->esize), h->esize));
     const long long nstrip = std::max(1, (p.nz + wout - 1) / wout);
     const long long nseg = (p.nr + sg - 1) / sg;
     const int rows = sg + std::min(12, p.nr - sg + 12);  // segment plus its pipeline rows
@@ -191,7 +191,7 @@ std::vector<WorkItem> build_items(const lbm_axi_s* h, const lbm_axi_launch& c, i
   for (int k = 0; k < h->n; ++k) {
     if (only_inst >= 0 && k != only_inst) continue;
     const auto& p = h->prm[k];
-    const int seg = c.seg_rows > 0 ? c.seg_rows : p.nr;
+    const int seg = std::min(c.seg_rows > 0 ? c.seg_rows : p.nr, max_item_rows(row_pitch(p.nz, h->esize), h->esize));
     const int nstrip = std::max(1, (p.nz + wout - 1) / wout);
     for (int s = 0; s < p.nr; s += seg)
       for (int q = 0; q < nstrip; ++q) {
@@ -260,8 +260,6 @@ hipError_t enqueue_sweep(lbm_axi_s* h, bool moments, int inst_for_moments, doubl
   SweepArgs<R> g{};
   g.fin = static_cast<const R*>(h->fbuf[h->cur]);
   g.fout = static_cast<R*>(h->fbuf[h->cur ^ 1]);
-  g.plane = h->plane;
-  g.sink = h->plane - kSinkElems;
   g.inst = h->d_inst;
   g.items = h->d_items;
   g.n_items = h->n_items;
@@ -333,24 +331,21 @@ lbm_status read_err(lbm_axi_s* h, int k = -1) {
   return LBM_OK;
 }
 
-// The step kernel addresses three direction planes per buffer descriptor with 32-bit
-// byte offsets, so three planes must span less than 4 GiB.
-bool offsets_fit(long long plane, int esize) { return 3.0 * (double)plane * (double)esize < 4294967296.0; }
+// The step kernel addresses the rows of a work item with 32-bit byte offsets from one
+// descriptor: a segment of at least 8 rows must fit (only rows of many megabytes fail).
+bool offsets_fit(const lbm_axi_params& p, int esize) { return max_item_rows(row_pitch(p.nz, esize), esize) >= 8; }
 
-size_t f_bytes_of(int n, const lbm_axi_params* params, int prec, long long* plane_out,
+size_t f_bytes_of(int n, const lbm_axi_params* params, int prec, long long* felems_out,
                   std::vector<long long>* bases) {
   long long off = 0;
   const int esize = prec == LBM_PREC_FP32 ? 4 : 8;
   for (int k = 0; k < n; ++k) {
     if (bases) bases->push_back(off);
-    const long long nn = (long long)row_pitch(params[k].nz, esize) * params[k].nr;
+    const long long nn = 9LL * row_pitch(params[k].nz, esize) * params[k].nr;
     off += (nn + 63) / 64 * 64;  // every instance starts on a 256-byte boundary
   }
-  // A tail of kSinkElems per plane past the last instance: the step kernel's halo lanes
-  // direct their (discarded) stores there instead of branching around them.
-  off += kSinkElems;
-  if (plane_out) *plane_out = off;
-  return (size_t)off * 9 * (prec == LBM_PREC_FP32 ? 4 : 8);
+  if (felems_out) *felems_out = off;
+  return (size_t)off * esize;
 }
 
 void free_all(lbm_axi_s* h) {
@@ -372,8 +367,7 @@ hipError_t unstream_into(lbm_axi_s* h, int k, const double* rho0, const double* 
                          const double* f0) {
   const auto& p = h->prm[k];
   R* dst = static_cast<R*>(h->fbuf[h->cur]) + h->base[k];
-  return launch_unstream<R>(dst, h->plane, p.nz, h->hinst[k].pitch, p.nr, p.bc_top, h->hinst[k].rho_ref, rho0,
-                            uz0, ur0, f0,
+  return launch_unstream<R>(dst, p.nz, h->hinst[k].pitch, p.nr, p.bc_top, h->hinst[k].rho_ref, rho0, uz0, ur0, f0,
                             h->stream);
 }
 
@@ -438,11 +432,12 @@ lbm_status create(int n, const lbm_axi_params* params, int prec, const double* c
   h->prec = prec;
   h->esize = prec == LBM_PREC_FP32 ? 4 : 8;
   h->prm.assign(params, params + n);
-  const size_t fb = f_bytes_of(n, params, prec, &h->plane, &h->base);
-  if (!offsets_fit(h->plane, h->esize)) {
-    delete h;
-    return LBM_ERR_UNSUPPORTED;
-  }
+  const size_t fb = f_bytes_of(n, params, prec, &h->felems, &h->base);
+  for (int k = 0; k < n; ++k)
+    if (!offsets_fit(params[k], (int)h->esize)) {
+      delete h;
+      return LBM_ERR_UNSUPPORTED;
+    }
   for (int k = 0; k < n; ++k) {
     const double rref = prec == LBM_PREC_FP32 ? reference_density(params[k], rho0[k]) : 0.0;
     h->hinst.push_back(make_inst(params[k], h->base[k], rref, h->esize));
@@ -512,8 +507,6 @@ hipError_t enqueue_moments(lbm_axi_s* h, int k, double* mr, double* mz, double* 
   SweepArgs<R> g{};
   g.fin = static_cast<const R*>(h->fbuf[h->cur]);
   g.fout = static_cast<R*>(h->fbuf[h->cur ^ 1]);
-  g.plane = h->plane;
-  g.sink = h->plane - kSinkElems;
   g.inst = h->d_inst;
   g.items = h->d_items;
   g.n_items = h->n_items;
@@ -561,9 +554,9 @@ lbm_status lbm_axi_workspace_bytes(int32_t n, const lbm_axi_params* params, int3
     lbm_status s = check_params(params[k]);
     if (s != LBM_OK) return s;
   }
-  long long plane = 0;
-  const size_t fb = f_bytes_of(n, params, precision, &plane, nullptr);
-  if (!offsets_fit(plane, precision == LBM_PREC_FP32 ? 4 : 8)) return LBM_ERR_UNSUPPORTED;
+  const size_t fb = f_bytes_of(n, params, precision, nullptr, nullptr);
+  for (int k = 0; k < n; ++k)
+    if (!offsets_fit(params[k], precision == LBM_PREC_FP32 ? 4 : 8)) return LBM_ERR_UNSUPPORTED;
   *bytes = 2 * fb;
   return LBM_OK;
 }
@@ -707,10 +700,10 @@ lbm_status lbm_axi_moments(lbm_axi_t h, int32_t k, double* rho, double* uz, doub
 
 static lbm_status reduce(lbm_axi_t h, int K, double* out) {
   hipError_t e = h->prec == LBM_PREC_FP32
-                     ? launch_rows<float>(K, static_cast<const float*>(h->fbuf[h->cur]), h->plane, h->d_inst,
-                                          h->d_rows, h->n_rows, h->d_geo, h->d_part, h->stream)
-                     : launch_rows<double>(K, static_cast<const double*>(h->fbuf[h->cur]), h->plane, h->d_inst,
-                                           h->d_rows, h->n_rows, h->d_geo, h->d_part, h->stream);
+                     ? launch_rows<float>(K, static_cast<const float*>(h->fbuf[h->cur]), h->d_inst, h->d_rows,
+                                          h->n_rows, h->d_geo, h->d_part, h->stream)
+                     : launch_rows<double>(K, static_cast<const double*>(h->fbuf[h->cur]), h->d_inst, h->d_rows,
+                                           h->n_rows, h->d_geo, h->d_part, h->stream);
   if (e != hipSuccess) return LBM_ERR_HIP;
   HIPCHK(launch_finish(K, h->d_part, h->d_row_start, h->d_inst, h->n, h->d_out, h->stream));
   HIPCHK(hipMemcpyAsync(out, h->d_out, h->n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -743,9 +736,9 @@ lbm_status lbm_axi_get_f(lbm_axi_t h, int32_t k, double* f) {
   HIPCHK(hipMalloc(&tmp, 9 * n * sizeof(double)));
   hipError_t e =
       h->prec == LBM_PREC_FP32
-          ? launch_export<float>(static_cast<const float*>(h->fbuf[h->cur]) + h->base[k], h->plane, p.nz,
-                                 h->hinst[k].pitch, p.nr, p.bc_top, h->hinst[k].rho_ref, tmp, h->stream)
-          : launch_export<double>(static_cast<const double*>(h->fbuf[h->cur]) + h->base[k], h->plane, p.nz,
+          ? launch_export<float>(static_cast<const float*>(h->fbuf[h->cur]) + h->base[k], p.nz, h->hinst[k].pitch,
+                                 p.nr, p.bc_top, h->hinst[k].rho_ref, tmp, h->stream)
+          : launch_export<double>(static_cast<const double*>(h->fbuf[h->cur]) + h->base[k], p.nz,
                                   h->hinst[k].pitch, p.nr, p.bc_top, h->hinst[k].rho_ref, tmp, h->stream);
   lbm_status st = LBM_OK;
   if (e != hipSuccess ||
@@ -783,7 +776,7 @@ lbm_status lbm_axi_sizes(lbm_axi_t h, int32_t* n, int64_t* nodes, int64_t* f_byt
   if (!h) return LBM_ERR_ARG;
   if (n) *n = h->n;
   if (nodes) *nodes = h->nodes;
-  if (f_bytes) *f_bytes = (int64_t)(h->plane * 9 * (long long)h->esize);
+  if (f_bytes) *f_bytes = (int64_t)(h->felems * (long long)h->esize);
   return LBM_OK;
 }
 
@@ -817,7 +810,7 @@ lbm_status lbm_axi_stream_copy(int64_t bytes, int32_t iters, double* gbps) {
 lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch* best, double* best_ms) {
   if (!h || steps_per_trial < 1) return LBM_ERR_ARG;
   HIPCHK(hipStreamSynchronize(h->stream));
-  const size_t fb = (size_t)h->plane * 9 * h->esize;
+  const size_t fb = (size_t)h->felems * h->esize;
   void* save = nullptr;
   HIPCHK(hipMalloc(&save, fb));
   const int cur0 = h->cur;

@@ -15,9 +15,11 @@ double eos_psi(const lbm_axi_params& p, double rho);  // sqrt(rho/3 - P_k), 0 fo
 
 // Per-instance constants as the kernels read them (uniform, loaded through the scalar cache).
 struct InstDev {
-  long long base;    // index of node (0, 0) of the instance inside every distribution plane
+  long long base;    // element index of the instance's first row block in a distribution buffer
   int nz, nr;
-  int pitch;         // elements from one row of a plane to the next (nz rounded up to 128 bytes)
+  int pitch;         // elements of one row of one plane (nz rounded up to 128 bytes); a row
+                     // block holds the nine planes' rows: element (i, row, col) at
+                     // base + (9 row + i) pitch + col
   int eos, axisym, faxis_sound, bc_top, forcing;
   // EOS in the form the kernels evaluate (FP64 in every precision):
   //   Carnahan-Starling  P = c1 rho n(e) / (1 - e)^3 - c2 rho^2, e = ce rho (c1 = lambda R T, c2 = lambda a, ce = b / 4)
@@ -41,6 +43,8 @@ struct WorkItem {
 // Rows of the distribution planes start on 128-byte boundaries and the step kernel's strips
 // of output columns are whole 128-byte lines, so that no line is written in part by two
 // workgroups (HBM has no byte masks: a partly written line costs a read-modify-write).
+// The nine planes of a row sit next to each other (a row block), so that the rows a
+// workgroup reads and writes in one step are close together in memory.
 inline int line_elems(int esize) { return 128 / esize; }
 inline int row_pitch(int nz, int esize) { return (nz + line_elems(esize) - 1) / line_elems(esize) * line_elems(esize); }
 inline int strip_cols(int width, int esize) {
@@ -48,17 +52,19 @@ inline int strip_cols(int width, int esize) {
   return (width - 12) / line_elems(esize) * line_elems(esize);
 }
 
-// Elements at the end of every distribution plane that belong to no instance (a sink for
-// the stores of the step kernel's halo lanes); at least the widest workgroup.
-constexpr long long kSinkElems = 256;
+// Rows of one work item of the step kernel (its segment plus 14 rows of pipeline and
+// gather halo) stay within 2 GiB of its load descriptor's base: the segment length cap.
+inline int max_item_rows(int pitch, int esize) {
+  const long long block = 9LL * pitch * esize;
+  const long long rows = (1LL << 31) / block - 14;
+  return rows > (1 << 30) ? (1 << 30) : (int)rows;
+}
 
 // Arguments of the fused step kernel.
 template <typename R>
 struct SweepArgs {
   const R* __restrict__ fin;   // post-collision planes of the previous step
   R* __restrict__ fout;        // post-collision planes of this step
-  long long plane;             // elements between consecutive direction planes
-  long long sink;              // plane index of the sink (plane - kSinkElems)
   const InstDev* __restrict__ inst;
   const WorkItem* __restrict__ items;
   int n_items;
@@ -78,14 +84,14 @@ template <typename R>
 hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool persist, bool regf, bool guo,
                           int grid, hipStream_t st);
 template <typename R>
-hipError_t launch_unstream(R* fout, long long P, int nz, int pitch, int nr, int bc_top, double rho_ref,
+hipError_t launch_unstream(R* fout, int nz, int pitch, int nr, int bc_top, double rho_ref,
                            const double* rho0,
                            const double* uz0, const double* ur0, const double* f0, hipStream_t st);
 template <typename R>
-hipError_t launch_export(const R* fin, long long P, int nz, int pitch, int nr, int bc_top, double rho_ref,
+hipError_t launch_export(const R* fin, int nz, int pitch, int nr, int bc_top, double rho_ref,
                          double* out, hipStream_t st);
 template <typename R>
-hipError_t launch_rows(int K, const R* fin, long long P, const InstDev* inst, const RowRef* rows,
+hipError_t launch_rows(int K, const R* fin, const InstDev* inst, const RowRef* rows,
                        int nrows, const double* geo, double* part, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, long long bytes, hipStream_t st);
 hipError_t launch_finish(int K, const double* part, const int* row_start, const InstDev* inst, int n,

@@ -94,16 +94,17 @@ __device__ __forceinline__ void eos_dev(const InstDev& I, double rho, double& P,
 }
 
 // Post-streaming populations of node (col, x) pulled from the post-collision
-// planes fin: f_i(x) = f*_i(x - c_i), with mid-grid specular reflection at the axis,
-// specular (free slip) or half-way bounce-back (no slip) at r = nr, periodic z.
-// cm, c0, cp are the wrapped columns k-1, k, k+1.  Row pointers are uniform across the
-// workgroup and the lane offsets are 32-bit, so the loads take a scalar base.
+// populations f of one instance: f_i(x) = f*_i(x - c_i), with mid-grid specular reflection
+// at the axis, specular (free slip) or half-way bounce-back (no slip) at r = nr, periodic z.
+// cm, c0, cp are the wrapped columns k-1, k, k+1.  Layout: row blocks of the nine direction
+// planes, element (i, row, col) at (9 row + i) pitch + col.
 template <typename R>
-__device__ __forceinline__ void gather(const R* __restrict__ f, long long P, int pitch, int nr, int bc_top,
+__device__ __forceinline__ void gather(const R* __restrict__ f, int pitch, int nr, int bc_top,
                                        int x, unsigned cm, unsigned c0, unsigned cp, R o[9]) {
-  const R* r0 = f + (long long)x * pitch;
-  const R* rm = x > 0 ? r0 - pitch : r0;       // row x-1 feeds the directions with c_r = +1
-  const R* rp = x < nr - 1 ? r0 + pitch : r0;  // row x+1 feeds the directions with c_r = -1
+  const long long P = pitch, rs = 9LL * pitch;
+  const R* r0 = f + (long long)x * rs;
+  const R* rm = x > 0 ? r0 - rs : r0;       // row x-1 feeds the directions with c_r = +1
+  const R* rp = x < nr - 1 ? r0 + rs : r0;  // row x+1 feeds the directions with c_r = -1
   o[0] = r0[c0];
   o[1] = (r0 + P)[cm];
   o[3] = (r0 + 3 * P)[cp];
@@ -131,24 +132,25 @@ __device__ __forceinline__ void gather(const R* __restrict__ f, long long P, int
   }
 }
 
-// The same pull map through raw buffer loads: three 128-bit descriptors, each covering
-// three consecutive direction planes of the instance, with the plane and the row as a
-// uniform byte offset and the column as a per-lane byte offset, so that no per-lane
-// address arithmetic is spent on the loads.  The host keeps 3 plane strides below 4 GiB.
+// The same pull map through raw buffer loads: one 128-bit descriptor based at the first
+// row block a work item touches, with the row and the plane as a uniform byte offset and
+// the column as a per-lane byte offset, so that no per-lane address arithmetic is spent on
+// the loads.  The host keeps the rows of a work item within 2 GiB of that base.
 template <typename R>
 struct Planes {
-  __amdgpu_buffer_rsrc_t g[3];
-  unsigned pstride;  // bytes between consecutive planes
+  __amdgpu_buffer_rsrc_t g;
+  unsigned pstride;  // bytes between consecutive planes of a row block
+  unsigned rstride;  // bytes between consecutive row blocks
 };
 
+// nbytes: the descriptor's range; a raw-buffer access at an offset past it is dropped by
+// the hardware (a store writes nothing, a load returns 0).
 template <typename R>
-__device__ __forceinline__ Planes<R> make_planes(const R* base, long long P) {
+__device__ __forceinline__ Planes<R> make_planes(const R* base, int pitch, unsigned nbytes = 0xffffffffu) {
   Planes<R> p;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-    p.g[i] = __builtin_amdgcn_make_buffer_rsrc(const_cast<R*>(base + 3 * i * P), (short)0, (int)0xffffffff,
-                                               (int)0x00020000);
-  p.pstride = (unsigned)(P * (long long)sizeof(R));
+  p.g = __builtin_amdgcn_make_buffer_rsrc(const_cast<R*>(base), (short)0, (int)nbytes, (int)0x00020000);
+  p.pstride = (unsigned)pitch * (unsigned)sizeof(R);
+  p.rstride = 9u * p.pstride;
   return p;
 }
 
@@ -167,65 +169,59 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsig
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
 }
 
-template <typename R>
-__device__ __forceinline__ void pstore(const Planes<R>& pl, int q, R v, unsigned voff, unsigned row_off) {
-  bstore(v, pl.g[q / 3], voff, row_off + (unsigned)(q % 3) * pl.pstride);
-}
 
-// bm, b0, bp: byte offsets of columns k-1, k, k+1 within a row.  The wall cases are
-// chosen with uniform selects of descriptor and offset (and, at a no-slip wall, of the
-// column), so that the nine loads form one straight sequence: the compiler can then
-// track them individually and overlap them with the stores still in flight.
+// bm, b0, bp: byte offsets of columns k-1, k, k+1 within a row; x0: the row the
+// descriptor is based at.  The wall cases are chosen with uniform selects of the plane
+// and row offsets (and, at a no-slip wall, of the column), so that the nine loads form one
+// straight sequence: the compiler can then track them individually and overlap them with
+// the stores still in flight.
 template <typename R>
-__device__ __forceinline__ void gather_b(const Planes<R>& pl, int pitch, int nr, int bc_top, int x, unsigned bm,
+__device__ __forceinline__ void gather_b(const Planes<R>& pl, int nr, int bc_top, int x, int x0, unsigned bm,
                                          unsigned b0, unsigned bp, R o[9]) {
-  const unsigned row = (unsigned)sizeof(R) * (unsigned)pitch, ps = pl.pstride;
-  const unsigned s0 = (unsigned)x * row;
+  const unsigned rs = pl.rstride, ps = pl.pstride;
+  const unsigned s0 = (unsigned)(x - x0) * rs;
   const bool axis = x == 0, top = x == nr - 1;
   const bool noslip = top && bc_top == LBM_TOP_NO_SLIP;
-  const unsigned sm = s0 - row, sp = s0 + row;
-  // plane q at row offset r: descriptor g[q / 3], scalar offset r + (q % 3) * ps
-  o[0] = bload(R(0), pl.g[0], b0, s0);
-  o[1] = bload(R(0), pl.g[0], bm, s0 + ps);
-  o[3] = bload(R(0), pl.g[1], bp, s0);
+  const unsigned sm = s0 - rs, sp = s0 + rs;
+  o[0] = bload(R(0), pl.g, b0, s0);
+  o[1] = bload(R(0), pl.g, bm, s0 + ps);
+  o[3] = bload(R(0), pl.g, bp, s0 + 3 * ps);
   // c_r = +1 from row x - 1; across the axis (c_z, +1) is (c_z, -1) of node (k - c_z, 0)
-  o[2] = bload(R(0), axis ? pl.g[1] : pl.g[0], b0, axis ? s0 + ps : sm + 2 * ps);       // 4 : 2
-  o[5] = bload(R(0), axis ? pl.g[2] : pl.g[1], bm, axis ? s0 + 2 * ps : sm + 2 * ps);   // 8 : 5
-  o[6] = bload(R(0), pl.g[2], bp, axis ? s0 + ps : sm);                                 // 7 : 6
+  o[2] = bload(R(0), pl.g, b0, axis ? s0 + 4 * ps : sm + 2 * ps);   // 4 : 2
+  o[5] = bload(R(0), pl.g, bm, axis ? s0 + 8 * ps : sm + 5 * ps);   // 8 : 5
+  o[6] = bload(R(0), pl.g, bp, axis ? s0 + 7 * ps : sm + 6 * ps);   // 7 : 6
   // c_r = -1 from row x + 1; at the wall from (c_z, +1) of node (k - c_z, nr - 1)
   // (specular) or of the same node with c_z reversed (bounce-back)
-  o[4] = bload(R(0), top ? pl.g[0] : pl.g[1], b0, top ? s0 + 2 * ps : sp + ps);         // 2 : 4
-  o[7] = bload(R(0), top ? (noslip ? pl.g[1] : pl.g[2]) : pl.g[2], noslip ? b0 : bp,
-               top ? (noslip ? s0 + 2 * ps : s0) : sp + ps);                            // 5 | 6 : 7
-  o[8] = bload(R(0), top ? (noslip ? pl.g[2] : pl.g[1]) : pl.g[2], noslip ? b0 : bm,
-               top ? (noslip ? s0 : s0 + 2 * ps) : sp + 2 * ps);                        // 6 | 5 : 8
+  o[4] = bload(R(0), pl.g, b0, top ? s0 + 2 * ps : sp + 4 * ps);    // 2 : 4
+  o[7] = bload(R(0), pl.g, noslip ? b0 : bp, top ? (noslip ? s0 + 5 * ps : s0 + 6 * ps) : sp + 7 * ps);  // 5 | 6 : 7
+  o[8] = bload(R(0), pl.g, noslip ? b0 : bm, top ? (noslip ? s0 + 6 * ps : s0 + 5 * ps) : sp + 8 * ps);  // 6 | 5 : 8
 }
 
 // gather_b for an interior row (0 < x < nr - 1): the same loads in the same order, without
-// the wall selects; gather() picks it for interior rows (a uniform branch).
+// the wall selects; gather_row() picks it for interior rows (a uniform branch).
 template <typename R>
-__device__ __forceinline__ void gather_interior(const Planes<R>& pl, int pitch, int x, unsigned bm, unsigned b0,
+__device__ __forceinline__ void gather_interior(const Planes<R>& pl, int x, int x0, unsigned bm, unsigned b0,
                                                 unsigned bp, R o[9]) {
-  const unsigned row = (unsigned)sizeof(R) * (unsigned)pitch, ps = pl.pstride;
-  const unsigned s0 = (unsigned)x * row, sm = s0 - row, sp = s0 + row;
-  o[0] = bload(R(0), pl.g[0], b0, s0);
-  o[1] = bload(R(0), pl.g[0], bm, s0 + ps);
-  o[3] = bload(R(0), pl.g[1], bp, s0);
-  o[2] = bload(R(0), pl.g[0], b0, sm + 2 * ps);
-  o[5] = bload(R(0), pl.g[1], bm, sm + 2 * ps);
-  o[6] = bload(R(0), pl.g[2], bp, sm);
-  o[4] = bload(R(0), pl.g[1], b0, sp + ps);
-  o[7] = bload(R(0), pl.g[2], bp, sp + ps);
-  o[8] = bload(R(0), pl.g[2], bm, sp + 2 * ps);
+  const unsigned rs = pl.rstride, ps = pl.pstride;
+  const unsigned s0 = (unsigned)(x - x0) * rs, sm = s0 - rs, sp = s0 + rs;
+  o[0] = bload(R(0), pl.g, b0, s0);
+  o[1] = bload(R(0), pl.g, bm, s0 + ps);
+  o[3] = bload(R(0), pl.g, bp, s0 + 3 * ps);
+  o[2] = bload(R(0), pl.g, b0, sm + 2 * ps);
+  o[5] = bload(R(0), pl.g, bm, sm + 5 * ps);
+  o[6] = bload(R(0), pl.g, bp, sm + 6 * ps);
+  o[4] = bload(R(0), pl.g, b0, sp + 4 * ps);
+  o[7] = bload(R(0), pl.g, bp, sp + 7 * ps);
+  o[8] = bload(R(0), pl.g, bm, sp + 8 * ps);
 }
 
 template <typename R>
-__device__ __forceinline__ void gather_row(const Planes<R>& pl, int pitch, int nr, int bc_top, int x, unsigned bm,
+__device__ __forceinline__ void gather_row(const Planes<R>& pl, int nr, int bc_top, int x, int x0, unsigned bm,
                                            unsigned b0, unsigned bp, R o[9]) {
   if (x > 0 && x < nr - 1)
-    gather_interior<R>(pl, pitch, x, bm, b0, bp, o);
+    gather_interior<R>(pl, x, x0, bm, b0, bp, o);
   else
-    gather_b<R>(pl, pitch, nr, bc_top, x, bm, b0, bp, o);
+    gather_b<R>(pl, nr, bc_top, x, x0, bm, b0, bp, o);
 }
 
 // Equilibrium of Sec. 2.1 (c_s^2 = 1/3) relative to the storage shift:
@@ -380,19 +376,25 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
   const unsigned col = (unsigned)wrapi(wi.k0 - 6 + min(lane, wi.ncols + 11), nz);
   const unsigned cm = (unsigned)wrapi((int)col - 1, nz), cp = (unsigned)wrapi((int)col + 1, nz);
   const bool out_lane = lane >= 6 && lane < 6 + wi.ncols;
-  const Planes<R> pin = make_planes<R>(g.fin + I.base, g.plane);
-  const Planes<R> pout = make_planes<R>(g.fout + I.base, g.plane);
+  const int s = wi.s, e = wi.e;
+  const int a_lo = max(0, s - 6), a_hi = min(nr, e + 6);
+  // gathers touch rows a_lo - 1 .. a_hi: the load descriptor is based at row block x0
+  const int x0 = max(0, a_lo - 1);
+  const long long rs = 9LL * I.pitch;  // elements between row blocks
+  const Planes<R> pin = make_planes<R>(g.fin + I.base + (long long)x0 * rs, I.pitch);
+  // stores: rows s .. e - 1, from the same row block; the range ends after row e - 1
+  const Planes<R> pout = make_planes<R>(g.fout + I.base + (long long)x0 * rs, I.pitch,
+                                        (unsigned)(e - x0) * (unsigned)(rs * (long long)sizeof(R)));
   const unsigned bcol = col * (unsigned)sizeof(R), bm = cm * (unsigned)sizeof(R), bp = cp * (unsigned)sizeof(R);
   // The strip that ends a row also fills the row's padding (columns nz .. pitch - 1, never
   // read) from its first halo lanes, so that the row's last line is written whole.
   const int ucol = wi.k0 - 6 + lane;
   const bool pad_lane = wi.k0 + wi.ncols == nz && ucol >= nz && ucol < I.pitch;
-  const unsigned bstore = pad_lane ? (unsigned)ucol * (unsigned)sizeof(R) : bcol;
-  // Other halo lanes store into the plane's sink (past every instance, one slot per lane)
-  // rather than skipping the stores, so every wave issues the same store sequence.
-  const unsigned sink_lane = (unsigned)((g.sink - I.base) * (long long)sizeof(R)) + (unsigned)lane * (unsigned)sizeof(R);
-  const int s = wi.s, e = wi.e;
-  const int a_lo = max(0, s - 6), a_hi = min(nr, e + 6);
+  const unsigned bst = pad_lane ? (unsigned)ucol * (unsigned)sizeof(R) : bcol;
+  // Other halo lanes (and idle pipeline steps) issue the same stores at an offset past the
+  // store descriptor's range, which the hardware drops: every wave then issues the same
+  // store sequence, which keeps the compiler's wait counts exact, without writing anything.
+  constexpr unsigned kDrop = 0x80000000u;
   const int b_lo = max(0, s - 4), b_hi = min(nr, e + 4);
   const int c_lo = max(0, s - 2), c_hi = min(nr, e + 2);
   const R omega = R(I.omega), nu = R(I.nu), gzf = R(I.gz), rho_ref = R(I.rho_ref);
@@ -429,11 +431,11 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
     for (int i = 0; i < 9; ++i) fd[a][i] = R(0);
 
   R fa[9], fg[9];
-  if (a_lo < a_hi) gather_row<R>(pin, I.pitch, nr, I.bc_top, a_lo, bm, bcol, bp, fa);
-  if (!REGF && !MOMENTS && s < e) gather_row<R>(pin, I.pitch, nr, I.bc_top, s, bm, bcol, bp, fg);
-  if (!MOMENTS) {  // the stores of a step, to the sink, so that loop entry looks like a loop iteration
+  if (a_lo < a_hi) gather_row<R>(pin, nr, I.bc_top, a_lo, x0, bm, bcol, bp, fa);
+  if (!REGF && !MOMENTS && s < e) gather_row<R>(pin, nr, I.bc_top, s, x0, bm, bcol, bp, fg);
+  if (!MOMENTS) {  // the (dropped) stores of a step, so that loop entry looks like a loop iteration
 #pragma unroll
-    for (int i = 0; i < 9; ++i) pstore(pout, i, __builtin_nondeterministic_value(R(0)), sink_lane, 0u);
+    for (int i = 0; i < 9; ++i) bstore(__builtin_nondeterministic_value(R(0)), pout.g, kDrop, i * pout.pstride);
   }
 
   for (int t = a_lo; t < e + 6; ++t) {
@@ -467,7 +469,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
 #pragma unroll
           for (int i = 0; i < 9; ++i) fd[0][i] = f[i];
         }
-        if (x + 1 < a_hi) gather_row<R>(pin, I.pitch, nr, I.bc_top, x + 1, bm, bcol, bp, fa);
+        if (x + 1 < a_hi) gather_row<R>(pin, nr, I.bc_top, x + 1, x0, bm, bcol, bp, fa);
         const double rd = I.rho_ref + (double)sg;  // rho in FP64 for the EOS
         double Pk, kap;
         eos_dev(I, rd, Pk, kap);
@@ -587,7 +589,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         } else {
 #pragma unroll
           for (int i = 0; i < 9; ++i) f[i] = fg[i];
-          if (x + 1 < e) gather_row<R>(pin, I.pitch, nr, I.bc_top, x + 1, bm, bcol, bp, fg);
+          if (x + 1 < e) gather_row<R>(pin, nr, I.bc_top, x + 1, x0, bm, bcol, bp, fg);
         }
         const R sg = sg_d[6], jz = jz_d[6], jr = jr_d[6];
         const R rho = rho_ref + sg;
@@ -608,12 +610,12 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         }
         collide<R>(f, rho, sg, jz, jr, fc2z, fc2r, m0, H3z, H3r, omega, GUO && I.forcing == LBM_FORCING_GUO, o);
       }
-      // Every iteration issues the same nine stores (to the sink while the stage idles or
-      // for halo lanes), which lets the compiler keep the prefetched loads in flight.
-      const unsigned orow = active ? (unsigned)x * (unsigned)sizeof(R) * (unsigned)I.pitch : 0u;
-      const unsigned voff = active && (out_lane || pad_lane) ? bstore : sink_lane - orow;
+      // Every iteration issues the same nine stores (dropped while the stage idles and for
+      // halo lanes), which lets the compiler keep the prefetched loads in flight.
+      const unsigned orow = active ? (unsigned)(x - x0) * pout.rstride : 0u;
+      const unsigned voff = active && (out_lane || pad_lane) ? bst : kDrop;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) pstore(pout, i, o[i], voff, orow);
+      for (int i = 0; i < 9; ++i) bstore(o[i], pout.g, voff, orow + i * pout.pstride);
     }
     {  // row t + 1 takes the slot of row t - 4
       const int r4 = rb[4];
@@ -703,7 +705,7 @@ __device__ __constant__ int c_opposite[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};  // c -
 // the inverse of the pull map.  f0 is either a double [9][nr][nz] array, or (when
 // f0 == nullptr) the equilibrium E(rho0, u0) of the initial fields (Sec. 2.1).
 template <typename R>
-__global__ void k_unstream(R* __restrict__ fout, long long P, int nz, int pitch, int nr, int bc_top, double rho_ref,
+__global__ void k_unstream(R* __restrict__ fout, int nz, int pitch, int nr, int bc_top, double rho_ref,
                            const double* __restrict__ rho0, const double* __restrict__ uz0,
                            const double* __restrict__ ur0, const double* __restrict__ f0) {
   const double wgt[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
@@ -737,14 +739,14 @@ __global__ void k_unstream(R* __restrict__ fout, long long P, int nz, int pitch,
                                     ur0 ? ur0[tn] : 0.0, e);
         v = e[ti];
       }
-      fout[i * P + (long long)j * pitch + k] = R(v);
+      fout[(9LL * j + i) * pitch + k] = R(v);
     }
   }
 }
 
 template <typename R>
-__global__ void k_export(const R* __restrict__ fin, long long P, int nz, int pitch, int nr, int bc_top,
-                         double rho_ref, double* __restrict__ out) {
+__global__ void k_export(const R* __restrict__ fin, int nz, int pitch, int nr, int bc_top, double rho_ref,
+                         double* __restrict__ out) {
   const double wgt[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
                          1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
   const long long n = (long long)nz * nr;
@@ -752,7 +754,7 @@ __global__ void k_export(const R* __restrict__ fin, long long P, int nz, int pit
        id += (long long)gridDim.x * blockDim.x) {
     const int k = (int)(id % nz), j = (int)(id / nz);
     R f[9];
-    gather<R>(fin, P, pitch, nr, bc_top, j, (unsigned)wrapi(k - 1, nz), (unsigned)k, (unsigned)wrapi(k + 1, nz), f);
+    gather<R>(fin, pitch, nr, bc_top, j, (unsigned)wrapi(k - 1, nz), (unsigned)k, (unsigned)wrapi(k + 1, nz), f);
     for (int i = 0; i < 9; ++i) out[i * n + id] = (double)f[i] + wgt[i] * rho_ref;
   }
 }
@@ -781,7 +783,7 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double (*sm)[K]) {
 
 // Per row: K = 1: sum_k rho; K = 4: (sum P_k, count) inside r_in and (sum P_k, count) beyond r_out.
 template <typename R, int K>
-__global__ void __launch_bounds__(256) k_rows(const R* __restrict__ fin, long long P,
+__global__ void __launch_bounds__(256) k_rows(const R* __restrict__ fin,
                                               const InstDev* __restrict__ inst,
                                               const RowRef* __restrict__ rows,
                                               const double* __restrict__ geo, double* __restrict__ part) {
@@ -796,7 +798,7 @@ __global__ void __launch_bounds__(256) k_rows(const R* __restrict__ fin, long lo
   const double rj = j + 0.5;
   for (int k = threadIdx.x; k < nz; k += 256) {
     R o[9];
-    gather<R>(f, P, I.pitch, I.nr, I.bc_top, j, (unsigned)wrapi(k - 1, nz), (unsigned)k, (unsigned)wrapi(k + 1, nz), o);
+    gather<R>(f, I.pitch, I.nr, I.bc_top, j, (unsigned)wrapi(k - 1, nz), (unsigned)k, (unsigned)wrapi(k + 1, nz), o);
     const R sg = o[0] + o[1] + o[2] + o[3] + o[4] + o[5] + o[6] + o[7] + o[8];
     const double rho = I.rho_ref + (double)sg;
     if (K == 1) {
@@ -911,46 +913,43 @@ template hipError_t sweep_dispatch<double>(const SweepArgs<double>&, int, bool, 
                                            hipStream_t);
 
 template <typename R>
-hipError_t launch_unstream(R* fout, long long P, int nz, int pitch, int nr, int bc_top, double rho_ref,
-                           const double* rho0, const double* uz0, const double* ur0, const double* f0,
-                           hipStream_t st) {
+hipError_t launch_unstream(R* fout, int nz, int pitch, int nr, int bc_top, double rho_ref, const double* rho0,
+                           const double* uz0, const double* ur0, const double* f0, hipStream_t st) {
   const long long n = (long long)nz * nr;
   const int grid = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
-  hipLaunchKernelGGL((k_unstream<R>), dim3(grid), dim3(256), 0, st, fout, P, nz, pitch, nr, bc_top, rho_ref,
+  hipLaunchKernelGGL((k_unstream<R>), dim3(grid), dim3(256), 0, st, fout, nz, pitch, nr, bc_top, rho_ref,
                      rho0, uz0, ur0, f0);
   return hipGetLastError();
 }
-template hipError_t launch_unstream<float>(float*, long long, int, int, int, int, double, const double*,
-                                           const double*, const double*, const double*, hipStream_t);
-template hipError_t launch_unstream<double>(double*, long long, int, int, int, int, double, const double*,
-                                            const double*, const double*, const double*, hipStream_t);
+template hipError_t launch_unstream<float>(float*, int, int, int, int, double, const double*, const double*,
+                                           const double*, const double*, hipStream_t);
+template hipError_t launch_unstream<double>(double*, int, int, int, int, double, const double*, const double*,
+                                            const double*, const double*, hipStream_t);
 
 template <typename R>
-hipError_t launch_export(const R* fin, long long P, int nz, int pitch, int nr, int bc_top, double rho_ref,
-                         double* out, hipStream_t st) {
+hipError_t launch_export(const R* fin, int nz, int pitch, int nr, int bc_top, double rho_ref, double* out,
+                         hipStream_t st) {
   const long long n = (long long)nz * nr;
   const int grid = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
-  hipLaunchKernelGGL((k_export<R>), dim3(grid), dim3(256), 0, st, fin, P, nz, pitch, nr, bc_top, rho_ref, out);
+  hipLaunchKernelGGL((k_export<R>), dim3(grid), dim3(256), 0, st, fin, nz, pitch, nr, bc_top, rho_ref, out);
   return hipGetLastError();
 }
-template hipError_t launch_export<float>(const float*, long long, int, int, int, int, double, double*,
-                                         hipStream_t);
-template hipError_t launch_export<double>(const double*, long long, int, int, int, int, double, double*,
-                                          hipStream_t);
+template hipError_t launch_export<float>(const float*, int, int, int, int, double, double*, hipStream_t);
+template hipError_t launch_export<double>(const double*, int, int, int, int, double, double*, hipStream_t);
 
 template <typename R>
-hipError_t launch_rows(int K, const R* fin, long long P, const InstDev* inst, const RowRef* rows, int nrows,
+hipError_t launch_rows(int K, const R* fin, const InstDev* inst, const RowRef* rows, int nrows,
                        const double* geo, double* part, hipStream_t st) {
   if (K == 1)
-    hipLaunchKernelGGL((k_rows<R, 1>), dim3(nrows), dim3(256), 0, st, fin, P, inst, rows, geo, part);
+    hipLaunchKernelGGL((k_rows<R, 1>), dim3(nrows), dim3(256), 0, st, fin, inst, rows, geo, part);
   else
-    hipLaunchKernelGGL((k_rows<R, 4>), dim3(nrows), dim3(256), 0, st, fin, P, inst, rows, geo, part);
+    hipLaunchKernelGGL((k_rows<R, 4>), dim3(nrows), dim3(256), 0, st, fin, inst, rows, geo, part);
   return hipGetLastError();
 }
-template hipError_t launch_rows<float>(int, const float*, long long, const InstDev*, const RowRef*, int,
-                                       const double*, double*, hipStream_t);
-template hipError_t launch_rows<double>(int, const double*, long long, const InstDev*, const RowRef*, int,
-                                        const double*, double*, hipStream_t);
+template hipError_t launch_rows<float>(int, const float*, const InstDev*, const RowRef*, int, const double*,
+                                       double*, hipStream_t);
+template hipError_t launch_rows<double>(int, const double*, const InstDev*, const RowRef*, int, const double*,
+                                        double*, hipStream_t);
 
 hipError_t launch_finish(int K, const double* part, const int* row_start, const InstDev* inst, int n,
                          double* out, hipStream_t st) {

@@ -95,3 +95,21 @@ def test_large_domain_full_size_tuned_launch(precision, large_oracle):
         assert max(er, eu) <= 1e-10
     else:
         assert er <= 5e-6 and eu <= 5e-5
+
+
+def test_fp64_domain_beyond_four_gib_per_three_planes():
+    # 16384 x 12288 in FP64 (201M nodes, 14.5 GB per distribution buffer): three direction
+    # planes span 4.8 GB, more than 32-bit offsets reach from one base; the step kernel
+    # rebases its descriptors per work item.  Whole-column segments (the segment cap then
+    # splits each column), two steps, every node against the oracle.
+    from paper_1512_01977_amd import lbm, workloads
+    wl = workloads.large_droplet(precision=0, nz=16384, nr=12288, radius=2500.0)
+    p, rho0 = wl.params[0], wl.rho0[0]
+    with lbm.LbmAxi(p, rho0, precision=0) as sim:
+        sim.set_launch(width=256, seg_rows=0, persistent=0, grid=0, xcd_swizzle=1, regf=0)
+        sim.step(LARGE_STEPS)
+        assert not sim.errors().any()
+        g = sim.moments(0)
+    er, eu = field_errors(g, oracle_moments(p, rho0, LARGE_STEPS))
+    print(f"16384 x 12288 FP64: rho err {er:.3e}, u err {eu:.3e}", flush=True)
+    assert max(er, eu) <= 1e-10

@@ -92,8 +92,9 @@ def test_tuning_size_class_keys():
 
 
 def test_workspace_sizing_and_offset_limit():
-    # Two buffers of nine planes; rows padded to 128 bytes, each instance to 64 elements,
-    # plus a 256-element sink per plane; layouts whose three planes would span 4 GiB are
+    # Two buffers; per instance nr row blocks of the nine planes, rows padded to 128 bytes,
+    # the instance padded to 64 elements.  A work item's rows are addressed with 32-bit
+    # offsets from one descriptor, so rows so wide that a 22-row item spans 2 GiB are
     # refused up front.
     import ctypes
     from paper_1512_01977_amd import lbm
@@ -105,13 +106,14 @@ def test_workspace_sizing_and_offset_limit():
         return L.lbm_axi_workspace_bytes(1, p, prec, ctypes.byref(nb)), nb.value
 
     st, nb = ws(16384, 8192, lbm.PREC_FP64)
-    assert st == 0 and nb == 2 * 9 * 8 * (16384 * 8192 + 256)
-    st, nb = ws(100, 7, lbm.PREC_FP32)                  # rows of 128 floats
-    assert st == 0 and nb == 2 * 9 * 4 * (896 + 256)
-    st, nb = ws(100, 7, lbm.PREC_FP64)                  # rows of 112 doubles
-    assert st == 0 and nb == 2 * 9 * 8 * (832 + 256)
-    assert ws(16384, 11000, lbm.PREC_FP64)[0] == -6     # 3 * plane * 8 B >= 4 GiB
-    assert ws(16384, 11000, lbm.PREC_FP32)[0] == 0
+    assert st == 0 and nb == 2 * 9 * 8 * 16384 * 8192
+    st, nb = ws(100, 7, lbm.PREC_FP32)                  # rows of 128 floats: 9 * 128 * 7 = 8064
+    assert st == 0 and nb == 2 * 4 * 8064
+    st, nb = ws(100, 7, lbm.PREC_FP64)                  # rows of 112 doubles: 7056 -> 7104
+    assert st == 0 and nb == 2 * 8 * 7104
+    assert ws(16384, 11000, lbm.PREC_FP64)[0] == 0
+    assert ws(1 << 21, 4, lbm.PREC_FP64)[0] == -6      # 22 row blocks of 151 MB exceed 2 GiB
+    assert ws(1 << 21, 4, lbm.PREC_FP32)[0] == 0
     assert ws(16384, 3, lbm.PREC_FP32)[0] == -1         # nr < 4
 
 
