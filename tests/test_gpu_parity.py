@@ -83,6 +83,39 @@ def test_launch_shapes_agree_with_oracle(launch):
     assert_fp64_parity(*run_pair(d, rho0, 120, launch=launch))
 
 
+def test_fp32_form_launch_shapes_agree_bitwise():
+    # The FP32 form in every launch shape of the list above on the same case: the
+    # decomposition into strips (whole 128-byte lines: 32 floats) and segments does not
+    # change what a node computes, so all shapes agree bitwise; and the result is within
+    # FP32 rounding of the FP64 oracle.
+    d = base(150, 37, A=-0.152, tau=0.9)
+    rho0 = droplet_rho(d, 11.0, eps=0.2, zc=70.0)
+    o, first = None, None
+    for launch in LAUNCHES:
+        print("case", launch, flush=True)
+        o, g = run_pair(d, rho0, 120, precision=1, launch=launch) if o is None else (o, run_pair_gpu(d, rho0, 120, 1, launch))
+        if first is None:
+            first = g
+            ro, uzo, uro, _ = o
+            uscale = max(np.abs(uzo).max(), np.abs(uro).max())
+            er = rel_inf(g[0], ro)
+            eu = max(np.abs(g[1] - uzo).max(), np.abs(g[2] - uro).max()) / uscale
+            print(f"FP32 vs oracle: rho {er:.2e}, u {eu:.2e}", flush=True)
+            assert er <= 1e-5 and eu <= 1e-4
+        else:
+            for a, b in zip(g, first):
+                assert np.array_equal(a, b), launch
+
+
+def run_pair_gpu(d, rho0, steps, precision, launch):
+    L = lbm()
+    with L.LbmAxi(gpu_params(d), rho0, precision=precision) as sim:
+        sim.set_launch(**launch)
+        sim.step(steps)
+        rg, uzg, urg = sim.moments()
+        return rg, uzg, urg, sim.get_f()
+
+
 VARIANTS = {
     "no_slip_top": dict(bc_top=1),
     "two_d": dict(axisym=0),
