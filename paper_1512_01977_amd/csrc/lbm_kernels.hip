@@ -3,8 +3,8 @@
 //
 // Fused step kernel ("sweep").  One workgroup of W lanes owns a strip of output
 // columns (z, contiguous in memory; whole 128-byte lines, at most W - 12 columns)
-// plus a 6-column halo on each side, and walks up the rows (r) of one segment.  Every iteration t advances four
-// pipeline stages that lag each other by two rows:
+// plus a 6-column halo on each side, and walks up the rows (r) of one segment.
+// Every iteration t advances four pipeline stages that lag each other by two rows:
 //   A (row t)    pull-gather the 9 populations with the wall maps, moments rho and
 //                j, EOS in FP64: P_k, kappa = dP_k/drho, psi = sqrt(rho/3 - P_k)
 //   B (row t-2)  D_z psi, D_r psi (eq. fifthorderaccuratefinitedifference) and
@@ -18,9 +18,10 @@
 // u_z, u_r); values a stage needs only at its own node travel in registers.
 // Ghost rows across the axis and the outer wall are written into the rings by the
 // producing stage with the field's mirror parity, so the stencils never branch.
-// Nothing but the populations touches HBM: one read and one write per node.  The
-// workgroup barriers order LDS only, and each row is gathered one iteration before it
-// is used, so the loads and stores stay in flight across the pipeline steps.
+// Nothing but the populations touches HBM: one read and one write per node, in row
+// blocks (the nine planes' rows of one r side by side).  The workgroup barriers order
+// LDS only, and each row is gathered one iteration before it is used, so the loads and
+// stores stay in flight across the pipeline steps.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
