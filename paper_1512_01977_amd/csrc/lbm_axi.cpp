@@ -840,7 +840,7 @@ lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch
   int maxnz = 0;
   for (auto& p : h->prm) maxnz = std::max(maxnz, p.nz);
   const int widths[] = {64, 128, 256};
-  const int segs[] = {32, 48, 64, 96, 128, 192, 256, 512, 0};
+  const int segs[] = {32, 40, 48, 64, 80, 96, 112, 128, 192, 256, 512, 0};
   for (int w : widths) {
     if (w > 64 && maxnz + 12 <= w / 2) continue;  // most lanes would duplicate columns
     for (int sg : segs)
