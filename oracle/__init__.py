@@ -113,6 +113,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_oracle_mass.argtypes = [P, dp, dp]
         L.lbm_oracle_laplace.argtypes = [P, dp, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, dp]
+        L.lbm_oracle_axis_interface.argtypes = [P, dp, ctypes.c_double, ctypes.c_double, dp]
         _lib = L
     return _lib
 
@@ -237,3 +238,11 @@ def laplace(p: Params, f: np.ndarray, zc: float, r_in: float, r_out: float) -> f
     _check(lib().lbm_oracle_laplace(ctypes.byref(p.c()), _ptr(f), zc, r_in, r_out,
                                     ctypes.byref(d)), "laplace")
     return d.value
+
+
+def axis_interface(p: Params, f: np.ndarray, zc: float, thr: float) -> float:
+    """Where rho on the axis row first falls to thr going +z from floor(zc) (Sec. 3.2)."""
+    z = ctypes.c_double()
+    _check(lib().lbm_oracle_axis_interface(ctypes.byref(p.c()), _ptr(f), zc, thr, ctypes.byref(z)),
+           "axis_interface")
+    return z.value

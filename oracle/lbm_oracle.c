@@ -614,6 +614,34 @@ int lbm_oracle_laplace(const lbm_oracle_params* p, const double* f, double zc, d
   return 0;
 }
 
+/* Sec. 3.2 tracks the oscillating drop by where its interface crosses the symmetry axis.
+ * Along the axis row (j = 0) from column k0 = floor(zc) towards +z: the first k >= k0
+ * whose next node has rho_{k+1} <= thr, and the linear interpolation of rho = thr between
+ * the two nodes, z = k + (rho_k - thr) / (rho_k - rho_{k+1}).  No such k before the last
+ * column gives NaN. */
+int lbm_oracle_axis_interface(const lbm_oracle_params* p, const double* f, double zc, double thr,
+                              double* z) {
+  int e = check_params(p);
+  if (e) return e;
+  if (!f || !z || !(zc >= 0.0) || !(zc < p->nz)) return ERR_ARG;
+  const int nz = p->nz;
+  const size_t n = (size_t)nz * p->nr;
+  const int k0 = (int)floor(zc);
+  *z = NAN;
+  for (int k = k0; k + 1 < nz; ++k) {
+    double rk = 0.0, rn = 0.0;
+    for (int i = 0; i < 9; ++i) {
+      rk += f[i * n + at(nz, k, 0)];
+      rn += f[i * n + at(nz, k + 1, 0)];
+    }
+    if (rn <= thr) {
+      *z = k + (rk - thr) / (rk - rn);
+      break;
+    }
+  }
+  return 0;
+}
+
 int lbm_oracle_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -111,6 +111,12 @@ int lbm_oracle_mass(const lbm_oracle_params* p, const double* f, double* mass);
 int lbm_oracle_laplace(const lbm_oracle_params* p, const double* f, double zc, double r_in,
                        double r_out, double* dp);
 
+/* Position of the drop's interface on the symmetry axis (Sec. 3.2): along row j = 0 from
+ * column floor(zc) towards +z, the first k whose next node has rho <= thr, interpolated
+ * linearly, z = k + (rho_k - thr) / (rho_k - rho_{k+1}); NaN if none before the last column. */
+int lbm_oracle_axis_interface(const lbm_oracle_params* p, const double* f, double zc, double thr,
+                              double* z);
+
 #ifdef __cplusplus
 }
 #endif

@@ -283,3 +283,24 @@ def test_static_droplet_axisymmetric_vs_2d():
     two_d = _static_dp_r(cs_params(96, 48, t=0.8, tau=1.0, axisym=0), 16.0, 2500)
     assert ax_ck == pytest.approx(two_d, rel=0.10)
     assert 1.3 < ax_cs / two_d < 2.05
+
+
+def test_axis_interface_closed_form():
+    # Populations at rest, f_i = w_i rho, so that the density of every node is rho: on the
+    # axis row a linear ramp rho_k = 1 - 0.1 k crosses thr = 0.55 between k = 4 and 5 at
+    # z = 4.5; other rows are irrelevant; zc picks the start column; rho_{k+1} == thr counts
+    # as the crossing (z = k + 1); no crossing gives NaN.
+    import numpy as np
+    p = O.Params(nz=12, nr=4, eos=O.EOS_IDEAL, tau=1.0)
+    rho = np.full((4, 12), 7.0)
+    rho[0] = 1.0 - 0.1 * np.arange(12)
+    f = np.ascontiguousarray(O.WEIGHTS[:, None, None] * rho[None])
+    assert O.axis_interface(p, f, 0.0, 0.55) == pytest.approx(4.5, abs=1e-12)
+    assert O.axis_interface(p, f, 2.7, 0.55) == pytest.approx(4.5, abs=1e-12)
+    assert O.axis_interface(p, f, 6.0, 0.55) == pytest.approx(6.0 + (0.4 - 0.55) / 0.1, abs=1e-12)
+    assert O.axis_interface(p, f, 0.0, 0.5) == pytest.approx(5.0, abs=1e-12)
+    rho[0] = np.linspace(2.0, 1.0, 12)
+    f = np.ascontiguousarray(O.WEIGHTS[:, None, None] * rho[None])
+    assert np.isnan(O.axis_interface(p, f, 0.0, 0.5))
+    with pytest.raises(O.OracleError):
+        O.axis_interface(p, f, -1.0, 0.5)
