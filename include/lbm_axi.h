@@ -187,6 +187,14 @@ lbm_status lbm_axi_mass(lbm_axi_t h, double* mass);
 lbm_status lbm_axi_laplace(lbm_axi_t h, const double* zc, const double* r_in,
                            const double* r_out, double* dp);
 
+/* Where each drop's interface crosses the symmetry axis, the observable Sec. 3.2 follows
+ * for the oscillating drop: on the axis row (j = 0), from column floor(zc[k]) towards +z,
+ * the first column k whose next node has rho <= thr[k], and z[k] = k + (rho_k - thr) /
+ * (rho_k - rho_{k+1}) (linear interpolation; NaN when no column before the last
+ * qualifies).  zc, thr, z: host [n] arrays.  Errors: LBM_ERR_ARG (zc outside [0, nz) or
+ * a non-finite thr); device errors as lbm_axi_sync.  Synchronising. */
+lbm_status lbm_axi_axis_interface(lbm_axi_t h, const double* zc, const double* thr, double* z);
+
 /* Checkpoint: the post-streaming populations of instance k as host double [9][nr][nz]. */
 lbm_status lbm_axi_get_f(lbm_axi_t h, int32_t k, double* f);
 

@@ -728,6 +728,27 @@ lbm_status lbm_axi_laplace(lbm_axi_t h, const double* zc, const double* r_in, co
   return reduce(h, 4, dp);
 }
 
+lbm_status lbm_axi_axis_interface(lbm_axi_t h, const double* zc, const double* thr, double* z) {
+  if (!h || !zc || !thr || !z) return LBM_ERR_ARG;
+  std::vector<double> geo(2 * h->n);
+  for (int k = 0; k < h->n; ++k) {
+    if (!(zc[k] >= 0.0) || !(zc[k] < h->prm[k].nz) || !std::isfinite(thr[k])) return LBM_ERR_ARG;
+    geo[2 * k] = zc[k];
+    geo[2 * k + 1] = thr[k];
+  }
+  HIPCHK(hipMemcpyAsync(h->d_geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  const hipError_t e =
+      h->prec == LBM_PREC_FP32
+          ? launch_axis<float>(static_cast<const float*>(h->fbuf[h->cur]), h->d_inst, h->n, h->d_geo, h->d_out,
+                               h->stream)
+          : launch_axis<double>(static_cast<const double*>(h->fbuf[h->cur]), h->d_inst, h->n, h->d_geo, h->d_out,
+                                h->stream);
+  if (e != hipSuccess) return LBM_ERR_HIP;
+  HIPCHK(hipMemcpyAsync(z, h->d_out, h->n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return read_err(h);
+}
+
 lbm_status lbm_axi_get_f(lbm_axi_t h, int32_t k, double* f) {
   if (!h || k < 0 || k >= h->n || !f) return LBM_ERR_ARG;
   const auto& p = h->prm[k];

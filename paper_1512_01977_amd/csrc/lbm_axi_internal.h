@@ -93,6 +93,8 @@ hipError_t launch_export(const R* fin, int nz, int pitch, int nr, int bc_top, do
 template <typename R>
 hipError_t launch_rows(int K, const R* fin, const InstDev* inst, const RowRef* rows,
                        int nrows, const double* geo, double* part, hipStream_t st);
+template <typename R>
+hipError_t launch_axis(const R* fin, const InstDev* inst, int n, const double* geo, double* out, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, long long bytes, hipStream_t st);
 hipError_t launch_finish(int K, const double* part, const int* row_start, const InstDev* inst, int n,
                          double* out, hipStream_t st);

@@ -824,6 +824,47 @@ __global__ void __launch_bounds__(256) k_rows(const R* __restrict__ fin,
     for (int q = 0; q < K; ++q) part[(long long)blockIdx.x * K + q] = acc[q];
 }
 
+// Sec. 3.2 follows the oscillating drop by where its interface crosses the symmetry axis.
+// One workgroup per instance: on the axis row, k* = the smallest k >= floor(zc) whose next
+// node has rho_{k+1} <= thr, then z = k* + (rho_k* - thr) / (rho_k* - rho_{k*+1}); NaN when
+// no column before the last qualifies.
+template <typename R>
+__global__ void __launch_bounds__(256) k_axis(const R* __restrict__ fin, const InstDev* __restrict__ inst,
+                                              const double* __restrict__ geo, double* __restrict__ out) {
+  __shared__ int s_k;
+  const int n = blockIdx.x;
+  const InstDev I = inst[n];
+  const int nz = I.nz;
+  const R* f = fin + I.base;
+  const double thr = geo[2 * n + 1];
+  const int k0 = (int)floor(geo[2 * n]);
+  auto rho_at = [&](int k) {
+    R o[9];
+    gather<R>(f, I.pitch, I.nr, I.bc_top, 0, (unsigned)wrapi(k - 1, nz), (unsigned)k, (unsigned)wrapi(k + 1, nz), o);
+    const R sg = o[0] + o[1] + o[2] + o[3] + o[4] + o[5] + o[6] + o[7] + o[8];
+    return I.rho_ref + (double)sg;
+  };
+  if (threadIdx.x == 0) s_k = 0x7fffffff;
+  __syncthreads();
+  int best = 0x7fffffff;
+  for (int k = k0 + (int)threadIdx.x; k + 1 < nz; k += 256)
+    if (rho_at(k + 1) <= thr) {  // the first hit of this lane's stride is its smallest
+      best = k;
+      break;
+    }
+  atomicMin(&s_k, best);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int k = s_k;
+    if (k == 0x7fffffff) {
+      out[n] = __builtin_nan("");
+    } else {
+      const double rk = rho_at(k), rn = rho_at(k + 1);
+      out[n] = k + (rk - thr) / (rk - rn);
+    }
+  }
+}
+
 // Per instance: combine its rows' partials in a fixed order.
 template <int K>
 __global__ void __launch_bounds__(256) k_finish(const double* __restrict__ part,
@@ -951,6 +992,14 @@ template hipError_t launch_rows<float>(int, const float*, const InstDev*, const 
                                        double*, hipStream_t);
 template hipError_t launch_rows<double>(int, const double*, const InstDev*, const RowRef*, int, const double*,
                                         double*, hipStream_t);
+
+template <typename R>
+hipError_t launch_axis(const R* fin, const InstDev* inst, int n, const double* geo, double* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_axis<R>), dim3(n), dim3(256), 0, st, fin, inst, geo, out);
+  return hipGetLastError();
+}
+template hipError_t launch_axis<float>(const float*, const InstDev*, int, const double*, double*, hipStream_t);
+template hipError_t launch_axis<double>(const double*, const InstDev*, int, const double*, double*, hipStream_t);
 
 hipError_t launch_finish(int K, const double* part, const int* row_start, const InstDev* inst, int n,
                          double* out, hipStream_t st) {

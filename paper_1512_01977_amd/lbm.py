@@ -33,7 +33,8 @@ EXPORTS = [
     "lbm_axi_batch_init", "lbm_axi_workspace_bytes", "lbm_axi_batch_init_ws", "lbm_axi_destroy",
     "lbm_axi_step", "lbm_axi_step_timed", "lbm_axi_sync", "lbm_axi_errors",
     "lbm_axi_set_graph_chunk",
-    "lbm_axi_moments", "lbm_axi_mass", "lbm_axi_laplace", "lbm_axi_get_f", "lbm_axi_set_f",
+    "lbm_axi_moments", "lbm_axi_mass", "lbm_axi_laplace", "lbm_axi_axis_interface",
+    "lbm_axi_get_f", "lbm_axi_set_f",
     "lbm_axi_get_launch", "lbm_axi_set_launch", "lbm_axi_autotune", "lbm_axi_stream_copy",
     "lbm_axi_sizes",
 ]
@@ -136,6 +137,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_axi_moments.argtypes = [_H, ctypes.c_int32, _dp, _dp, _dp]
         L.lbm_axi_mass.argtypes = [_H, _dp]
         L.lbm_axi_laplace.argtypes = [_H, _dp, _dp, _dp, _dp]
+        L.lbm_axi_axis_interface.argtypes = [_H, _dp, _dp, _dp]
         L.lbm_axi_get_f.argtypes = [_H, ctypes.c_int32, _dp]
         L.lbm_axi_set_f.argtypes = [_H, ctypes.c_int32, _dp]
         L.lbm_axi_get_launch.argtypes = [_H, LP]
@@ -298,6 +300,15 @@ class LbmAxi:
         _check(lib().lbm_axi_laplace(self.h, _ptr(zc), _ptr(r_in), _ptr(r_out), _ptr(dp)),
                "lbm_axi_laplace")
         return dp
+
+    def axis_interface(self, zc, thr) -> np.ndarray:
+        """Per instance, where rho on the axis row first falls to thr going +z from
+        floor(zc) (the drop's interface on the symmetry axis, Sec. 3.2)."""
+        zc, thr = (np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.float64), (self.n,)))
+                   for v in (zc, thr))
+        z = np.empty(self.n)
+        _check(lib().lbm_axi_axis_interface(self.h, _ptr(zc), _ptr(thr), _ptr(z)), "lbm_axi_axis_interface")
+        return z
 
     def get_f(self, k: int = 0) -> np.ndarray:
         p = self.params[k]

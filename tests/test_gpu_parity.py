@@ -177,6 +177,36 @@ def test_mass_and_laplace_match_oracle():
     assert dp == pytest.approx(O.laplace(po, f, 48.0, 8.0, 28.0), rel=1e-9)
 
 
+def test_axis_interface_matches_oracle():
+    # The drop's interface on the axis (Sec. 3.2) in a batch: a P2-stretched drop in FP64
+    # (against the oracle on the same populations), the same drop in FP32 (against the
+    # FP64 value, to FP32 rounding of the densities), and a threshold below the vapour
+    # density (no crossing: NaN on both sides).  zc outside the domain is refused.
+    L = lbm()
+    d = base(96, 48, A=-0.152)
+    rho0 = droplet_rho(d, 16.0, eps=0.2, zc=48.0)
+    rv, rl, _ = O.coexistence(oracle_params(d))
+    thr = 0.5 * (rv + rl)
+    po = oracle_params(d)
+    f = O.init(po, rho0)
+    O.step(po, f, 200)
+    z_o = O.axis_interface(po, f, 48.0, thr)
+    assert np.isnan(O.axis_interface(po, f, 48.0, 0.5 * rv))
+    got = {}
+    for prec in (0, 1):
+        with L.LbmAxi([gpu_params(d), gpu_params(d)], [rho0, rho0], precision=prec) as sim:
+            sim.step(200)
+            z = sim.axis_interface([48.0, 48.0], [thr, 0.5 * rv])
+            with pytest.raises(L.LbmError):
+                sim.axis_interface([48.0, 96.0], [thr, thr])
+        assert np.isnan(z[1])
+        got[prec] = z[0]
+    print(f"axis interface: oracle {z_o:.12f}, FP64 {got[0]:.12f}, FP32 {got[1]:.9f}", flush=True)
+    assert 48.0 + 12.0 < z_o < 48.0 + 24.0
+    assert got[0] == pytest.approx(z_o, rel=1e-10)
+    assert got[1] == pytest.approx(z_o, abs=1e-3)
+
+
 def test_checkpoint_round_trip_bitwise():
     L = lbm()
     d = base(64, 32, A=-0.152)
