@@ -85,7 +85,8 @@ typedef struct {
 typedef struct {
   int32_t width;        /* lanes per workgroup along z: 64, 128 or 256; a workgroup writes the
                            whole 128-byte lines that fit in width - 12 columns (12 are halo) */
-  int32_t seg_rows;     /* rows of r per work item (>= 8), 0 = whole column */
+  int32_t seg_rows;     /* rows of r per work item (>= 8), 0 = whole column; capped so that
+                           a work item's rows span less than 2 GiB (wide FP64 rows) */
   int32_t persistent;   /* 1: persistent grid draining a work queue; 0: one workgroup per item */
   int32_t grid;         /* persistent grid size, 0 = automatic */
   int32_t xcd_swizzle;  /* 1: neighbouring work items go to the same XCD; 0: items longest
