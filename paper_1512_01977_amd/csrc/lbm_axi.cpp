@@ -371,7 +371,7 @@ hipError_t unstream_into(lbm_axi_s* h, int k, const double* rho0, const double* 
                             h->stream);
 }
 
-// Upload host fields of instance k into a temporary device buffer and build its planes.
+// Upload host fields of instance k into a temporary device buffer and build its populations.
 lbm_status load_instance(lbm_axi_s* h, int k, const double* rho0, const double* uz0, const double* ur0,
                          const double* f0) {
   const auto& p = h->prm[k];
