@@ -90,7 +90,10 @@ typedef struct {
   int32_t persistent;   /* 1: persistent grid draining a work queue; 0: one workgroup per item */
   int32_t grid;         /* persistent grid size, 0 = automatic */
   int32_t xcd_swizzle;  /* 1: neighbouring work items go to the same XCD; 0: items longest
-                           first, dealt round-robin over the XCDs (better balance) */
+                           first, dealt round-robin over the XCDs (better balance); 2: longest
+                           first, the strips of one row band on one XCD (their shared edge
+                           lines stay in its L2); other values: LBM_ERR_ARG.  Ignored by the
+                           persistent grid, which always takes items longest first */
   int32_t regf;         /* 1: carry gathered populations in registers (no second gather) */
 } lbm_axi_launch;
 

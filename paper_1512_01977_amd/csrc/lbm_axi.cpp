@@ -183,6 +183,38 @@ lbm_axi_launch default_launch(const lbm_axi_s* h) {
   return best;
 }
 
+// Reorder a longest-first item list for a launch of one workgroup per item.  The hardware
+// hands workgroup b to XCD b % 8, and each XCD has its own L2.  Neighbouring strips of one
+// row band (same instance, same segment) read each other's edge lines, so the strips of a
+// band go to one XCD, where they run at about the same time and the shared lines come from
+// its L2 instead of HBM.  Bands are dealt in order to the XCD with the most room left; each
+// XCD keeps the list's longest-first order, and XCD x receives exactly the items at
+// positions x, x + 8, ... (a band that does not fit in the room left is split).
+std::vector<WorkItem> deal_over_xcds(const std::vector<WorkItem>& items) {
+  constexpr int kXcd = 8;
+  const size_t n = items.size();
+  std::vector<WorkItem> per[kXcd];
+  size_t room[kXcd];
+  for (int x = 0; x < kXcd; ++x) room[x] = n / kXcd + ((size_t)x < n % kXcd ? 1 : 0);
+  for (size_t i = 0; i < n;) {
+    size_t j = i + 1;
+    while (j < n && items[j].inst == items[i].inst && items[j].s == items[i].s) ++j;
+    while (i < j) {
+      int x = 0;
+      for (int y = 1; y < kXcd; ++y)
+        if (room[y] > room[x]) x = y;
+      const size_t take = std::min(room[x], j - i);
+      per[x].insert(per[x].end(), items.begin() + i, items.begin() + i + take);
+      room[x] -= take;
+      i += take;
+    }
+  }
+  std::vector<WorkItem> out(n);
+  for (int x = 0; x < kXcd; ++x)
+    for (size_t k = 0; k < per[x].size(); ++k) out[k * kXcd + x] = per[x][k];
+  return out;
+}
+
 // Strips of whole 128-byte lines of output columns (at most width - 12) times row
 // segments, for every instance.
 std::vector<WorkItem> build_items(const lbm_axi_s* h, const lbm_axi_launch& c, int only_inst) {
@@ -204,13 +236,14 @@ std::vector<WorkItem> build_items(const lbm_axi_s* h, const lbm_axi_launch& c, i
         items.push_back(w);
       }
   }
-  if (c.persistent || !c.xcd_swizzle) {
+  if (c.persistent || c.xcd_swizzle != 1) {
     // longest first (rows swept, halo included), so the queue drains evenly; without the
     // XCD swizzle the hardware deals consecutive workgroups round-robin over the XCDs, so
     // the same order balances a one-item-per-workgroup launch too
     auto cost = [](const WorkItem& w) { return (w.e - w.s) + std::min(6, w.s) + 6; };
     std::stable_sort(items.begin(), items.end(),
                      [&](const WorkItem& a, const WorkItem& b) { return cost(a) > cost(b); });
+    if (!c.persistent && c.xcd_swizzle == 2) return deal_over_xcds(items);
   }
   return items;
 }
@@ -240,7 +273,7 @@ void drop_graph(lbm_axi_s* h) {
 lbm_status apply_launch(lbm_axi_s* h, const lbm_axi_launch& c) {
   if (!valid_width(c.width)) return LBM_ERR_UNSUPPORTED;
   if (c.seg_rows != 0 && c.seg_rows < 8) return LBM_ERR_ARG;
-  if (c.grid < 0 || (c.regf != 0 && c.regf != 1)) return LBM_ERR_ARG;
+  if (c.grid < 0 || (c.regf != 0 && c.regf != 1) || c.xcd_swizzle < 0 || c.xcd_swizzle > 2) return LBM_ERR_ARG;
   lbm_status s = upload_items(h, build_items(h, c, -1));
   if (s != LBM_OK) return s;
   h->launch = c;
@@ -263,7 +296,7 @@ hipError_t enqueue_sweep(lbm_axi_s* h, bool moments, int inst_for_moments, doubl
   g.inst = h->d_inst;
   g.items = h->d_items;
   g.n_items = h->n_items;
-  g.xcd_swizzle = h->launch.xcd_swizzle;
+  g.xcd_swizzle = h->launch.xcd_swizzle == 1;
   g.queue = h->d_queue;
   g.err = h->d_err;
   g.mrho = mr;
@@ -865,11 +898,12 @@ lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch
   for (int w : widths) {
     if (w > 64 && maxnz + 12 <= w / 2) continue;  // most lanes would duplicate columns
     for (int sg : segs)
-      for (int v = 0; v < 6 && st == LBM_OK; ++v) {
-        // v: bit 0 persistent, bit 1 populations in registers; v >= 4: one item per
-        // workgroup, longest first, no XCD swizzle
+      for (int v = 0; v < 8 && st == LBM_OK; ++v) {
+        // v < 4: bit 0 persistent, bit 1 populations in registers (XCD swizzle);
+        // v >= 4: one item per workgroup, longest first, bit 0 populations in registers,
+        // bit 1 row bands kept on one XCD
         const lbm_axi_launch c = v < 4 ? lbm_axi_launch{w, sg, v & 1, 0, 1, v >> 1}
-                                       : lbm_axi_launch{w, sg, 0, 0, 0, v & 1};
+                                       : lbm_axi_launch{w, sg, 0, 0, v >= 6 ? 2 : 0, v & 1};
         double ms = 0.0;
         const lbm_status s = trial(c, steps_per_trial, &ms);
         if (s == LBM_ERR_HIP) st = s;

@@ -70,11 +70,14 @@ LAUNCHES = [
     dict(width=128, seg_rows=9, persistent=1, xcd_swizzle=0, regf=0),
     dict(width=256, seg_rows=13, persistent=1, xcd_swizzle=1, regf=0),
     dict(width=256, seg_rows=20, persistent=0, xcd_swizzle=1, regf=1),
+    dict(width=128, seg_rows=24, persistent=0, xcd_swizzle=2, regf=1),
+    dict(width=64, seg_rows=11, persistent=0, xcd_swizzle=2, regf=0),
 ]
 
 
 @pytest.mark.parametrize("launch", LAUNCHES,
-                         ids=lambda c: f"w{c['width']}s{c['seg_rows']}p{c['persistent']}r{c['regf']}")
+                         ids=lambda c: f"w{c['width']}s{c['seg_rows']}p{c['persistent']}"
+                                       f"x{c['xcd_swizzle']}r{c['regf']}")
 def test_launch_shapes_agree_with_oracle(launch):
     # strips with ragged tails (nz = 150 is no multiple of width - 12) and row segments
     d = base(150, 37, A=-0.152, tau=0.9)
@@ -240,6 +243,14 @@ def test_batch_members_equal_single_runs_bitwise():
                 one.step(60)
                 assert np.array_equal(one.get_f(), fb[k]), (prec, k)
                 assert one.mass()[0] == mb[k]
+        # one workgroup per item in each of the three item orders (XCD runs, longest first,
+        # longest first with row bands kept on one XCD): the same result bitwise
+        for xs in (0, 1, 2):
+            with L.LbmAxi([gpu_params(d) for d in ds], rhos, precision=prec) as bat:
+                bat.set_launch(width=64, seg_rows=10, persistent=0, grid=0, xcd_swizzle=xs, regf=xs & 1)
+                bat.step(60)
+                for k in range(len(ds)):
+                    assert np.array_equal(bat.get_f(k), fb[k]), (prec, xs, k)
 
 
 def test_mixed_forcing_batch_equals_single_runs_bitwise():
@@ -374,3 +385,10 @@ def test_host_rejects_bad_input():
     with pytest.raises(L.LbmError) as e:
         L.LbmAxi(gpu_params(base(16, 8, tau=0.4)), np.full((8, 16), 0.1))
     assert e.value.code == -1
+    with L.LbmAxi(gpu_params(base(16, 8)), np.full((8, 16), 0.1)) as sim:
+        keep = sim.get_launch()
+        for bad_launch in (dict(xcd_swizzle=3), dict(xcd_swizzle=-1), dict(regf=2), dict(seg_rows=5)):
+            with pytest.raises(L.LbmError) as e:
+                sim.set_launch(**{**keep, **bad_launch})
+            assert e.value.code == -1, bad_launch
+        assert sim.get_launch() == keep
