@@ -49,9 +49,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, dtype: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when
-    there is none for this workload or the kernel source changed since it was taken."""
+def traffic_record(workload: str, dtype: str):
+    """The committed rocprofv3 counter summary of this workload (HBM bytes per launch and
+    the launch shape they were counted in), or None when there is none or the kernel
+    source changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             data = json.load(fh)
@@ -60,10 +61,13 @@ def measured_traffic(workload: str, dtype: str):
     rec = data.get(f"{workload}:{dtype}")
     if not rec or rec.get("kernel_hash") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
 
 
-def run_form(wl, steps, warmup, graph_chunk, tune, label):
+def run_form(wl, steps, warmup, graph_chunk, shape, label):
+    """shape: "profiled" runs the launch shape the committed byte counters were taken in
+    (autotuning when there is none for the current kernel), "tune" autotunes unless the
+    tuning cache has this size class, "cached" takes the cache or the library's default."""
     import torch
     from paper_1512_01977_amd import lbm, tuning
 
@@ -73,8 +77,14 @@ def run_form(wl, steps, warmup, graph_chunk, tune, label):
     sim = lbm.LbmAxi(wl.params if len(wl.params) > 1 else wl.params[0],
                      wl.rho0 if len(wl.params) > 1 else wl.rho0[0], precision=wl.precision)
     log(f"[bench] {label}: state on the device in {time.perf_counter() - t0:.1f} s")
-    launch = tuning.choose_launch(sim, wl, tune=tune, log=log)
-    log(f"[bench] {label}: launch {launch}")
+    rec = traffic_record(wl.name, dtype)
+    if shape == "profiled" and rec and rec.get("launch"):
+        sim.set_launch(**rec["launch"])
+        launch, source = sim.get_launch(), "profiled"
+    else:
+        launch = tuning.choose_launch(sim, wl, tune=shape != "cached", log=log)
+        source = "tuner" if shape != "cached" else "cached"
+    log(f"[bench] {label}: launch {launch} ({source})")
     if graph_chunk:
         sim.set_graph_chunk(graph_chunk)
     sim.step(warmup)
@@ -90,14 +100,15 @@ def run_form(wl, steps, warmup, graph_chunk, tune, label):
     nodes = wl.nodes
     per_launch_s = ev_ms / 1e3 / steps
     achieved = BYTES_PER_NODE[dtype] * nodes / per_launch_s / 1e9
-    traffic = measured_traffic(wl.name, dtype)
+    # the counted bytes belong to one launch shape: reported only when that shape ran
+    traffic = rec.get("bytes_per_launch") if rec and rec.get("launch") == launch else None
     res = {
         "workload": wl.name, "dtype": dtype, "nodes": nodes, "steps": steps,
         "ms_per_step": wall * 1e3 / steps, "kernel_ms_per_step": ev_ms / steps,
         "MLUPS": nodes * steps / wall / 1e6,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic},
-        "launch": launch, "mass_after": mass,
+        "launch": launch, "launch_source": source, "mass_after": mass,
     }
     log(f"[bench] {label}: {res['MLUPS']:.0f} MLUPS, {achieved:.0f} GB/s algorithmic "
         f"({100 * achieved / HBM_PEAK_GBPS:.1f}% of HBM peak)")
@@ -172,6 +183,9 @@ def main():
     ap.add_argument("--forms", default="all", choices=["all", "main"],
                     help="all: also time the large single domain in FP32 and FP64")
     ap.add_argument("--graph-chunk", type=int, default=100)
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the launch shape (unless cached) instead of running the shape "
+                         "the committed byte counters were taken in")
     ap.add_argument("--no-tune", action="store_true", help="use the cached or default launch shape")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stream-copy", type=int, default=0, metavar="BYTES",
@@ -202,7 +216,8 @@ def main():
     t_all = time.perf_counter()
     wl = workloads.REGISTRY[args.workload](precision=main_prec)
     chunk = args.graph_chunk if args.steps >= args.graph_chunk else 0
-    main_res = run_form(wl, args.steps, args.warmup, chunk, not args.no_tune, "main")
+    shape = "cached" if args.no_tune else "tune" if args.tune else "profiled"
+    main_res = run_form(wl, args.steps, args.warmup, chunk, shape, "main")
 
     forms = [main_res]
     if args.forms == "all":
@@ -210,13 +225,13 @@ def main():
             if w_name == args.workload and prec[p_name] == main_prec:
                 continue
             w = workloads.REGISTRY[w_name](precision=prec[p_name])
-            forms.append(run_form(w, steps, 4, 0, not args.no_tune, f"{w_name}-{p_name}"))
+            forms.append(run_form(w, steps, 4, 0, shape, f"{w_name}-{p_name}"))
             del w
         # the 16384 x 8192 domain in FP32 with Guo's forcing (Sec. 2.1) in place of the
         # exact-difference method, at T/T_c = 0.8 (density ratio ~14): Guo's term does not
         # hold the ratio-1e3 droplet of the other forms
         try:
-            forms.append(run_form(guo_workload(), 100, 4, 0, not args.no_tune, "large-fp32-guo"))
+            forms.append(run_form(guo_workload(), 100, 4, 0, shape, "large-fp32-guo"))
         except Exception as exc:  # a form that fails is reported, the others still count
             log(f"[bench] large-fp32-guo: failed ({exc})")
 
@@ -246,13 +261,15 @@ def main():
         "dtype": main_res["dtype"],
         "data": "synthetic (seeded initial conditions of the paper's validation set-ups)",
         "config": {"workload": wl.name, "nodes": wl.nodes, "instances": len(wl.params),
-                   "graph_chunk": chunk, "launch": main_res["launch"]},
+                   "graph_chunk": chunk, "launch": main_res["launch"],
+                   "launch_source": main_res["launch_source"]},
         "roofline": main_res["roofline"],
         "stream_copy_GBps": copy_gbps,
         "cpu_baseline": cpu,
         "cpu_baseline_1core": cpu1,
         "forms": [{k: f[k] for k in ("workload", "dtype", "MLUPS", "ms_per_step",
-                                     "kernel_ms_per_step", "roofline", "launch")} for f in forms],
+                                     "kernel_ms_per_step", "roofline", "launch", "launch_source")}
+                  for f in forms],
         "wall_s": time.perf_counter() - t_all,
     }
     print(json.dumps(out), flush=True)
