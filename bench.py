@@ -64,6 +64,15 @@ def traffic_record(workload: str, dtype: str):
     return rec
 
 
+def same_launch(a, b) -> bool:
+    """Two launch-shape dicts name the same launch (a missing stream count reads as 1)."""
+    if not a or not b:
+        return False
+    keys = set(a) | set(b)
+    return all(a.get(k, 1 if k == "streams" else None) == b.get(k, 1 if k == "streams" else None)
+               for k in keys)
+
+
 def run_form(wl, steps, warmup, graph_chunk, shape, label):
     """shape: "profiled" runs the launch shape the committed byte counters were taken in
     (autotuning when there is none for the current kernel), "tune" autotunes unless the
@@ -101,7 +110,7 @@ def run_form(wl, steps, warmup, graph_chunk, shape, label):
     per_launch_s = ev_ms / 1e3 / steps
     achieved = BYTES_PER_NODE[dtype] * nodes / per_launch_s / 1e9
     # the counted bytes belong to one launch shape: reported only when that shape ran
-    traffic = rec.get("bytes_per_launch") if rec and rec.get("launch") == launch else None
+    traffic = rec.get("bytes_per_launch") if rec and same_launch(rec.get("launch"), launch) else None
     res = {
         "workload": wl.name, "dtype": dtype, "nodes": nodes, "steps": steps,
         "ms_per_step": wall * 1e3 / steps, "kernel_ms_per_step": ev_ms / steps,

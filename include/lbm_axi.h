@@ -95,6 +95,13 @@ typedef struct {
                            lines stay in its L2); other values: LBM_ERR_ARG.  Ignored by the
                            persistent grid, which always takes items longest first */
   int32_t regf;         /* 1: carry gathered populations in registers (no second gather) */
+  int32_t streams;      /* 1 (or 0): one launch per step for all instances; 2..4: the instances
+                           of a batch split into this many groups of about equal node counts,
+                           each stepped by its own launches on its own stream (created by the
+                           library, default priority), forked from and joined back into the
+                           handle's stream, so that one group's last work items overlap the
+                           others' next step.  Needs streams <= number of instances, else
+                           LBM_ERR_ARG.  Results do not depend on it. */
 } lbm_axi_launch;
 
 typedef struct lbm_axi_s* lbm_axi_t;

@@ -13,6 +13,8 @@
 
 using namespace lbm;
 
+constexpr int kMaxStreams = 4;
+
 struct lbm_axi_s {
   int n = 0;
   int prec = LBM_PREC_FP64;
@@ -43,8 +45,20 @@ struct lbm_axi_s {
   lbm_axi_launch launch{};
   int cus = 256;
   int graph_chunk = 0;
-  hipGraphExec_t gexec = nullptr;
   bool any_guo = false;  // some instance uses Guo's forcing: launch the kernel that can apply it
+  // Stream groups: with launch.streams > 1 the instances of a batch are split into groups,
+  // each stepped by launches of its own on a stream of its own (group 0 on `stream`), so that
+  // the last work items of one group's step overlap the next step of the others.  Steps fork
+  // from and join back into `stream`, which every other operation of the handle uses.
+  struct Group {
+    hipStream_t st = nullptr;  // group 0: the handle's stream (not owned by the group)
+    hipEvent_t done = nullptr;
+    int first = 0, count = 0;  // the group's work items in d_items
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // graph_chunk steps starting from fbuf[0] / fbuf[1]
+  };
+  Group grp[kMaxStreams];
+  int n_groups = 1;
+  hipEvent_t fork = nullptr;
 };
 
 namespace {
@@ -177,7 +191,7 @@ lbm_axi_launch default_launch(const lbm_axi_s* h) {
       const double t = std::max((double)lane_iters / cap, longest / 3.0);
       if (t < best_t * 0.999) {
         best_t = t;
-        best = lbm_axi_launch{w, sg, h->n > 1 ? 1 : 0, 0, 1, 0};
+        best = lbm_axi_launch{w, sg, h->n > 1 ? 1 : 0, 0, 1, 0, 1};
       }
     }
   return best;
@@ -216,12 +230,12 @@ std::vector<WorkItem> deal_over_xcds(const std::vector<WorkItem>& items) {
 }
 
 // Strips of whole 128-byte lines of output columns (at most width - 12) times row
-// segments, for every instance.
-std::vector<WorkItem> build_items(const lbm_axi_s* h, const lbm_axi_launch& c, int only_inst) {
+// segments, for the instances k with keep[k] != 0 (every instance when keep is empty).
+std::vector<WorkItem> build_items(const lbm_axi_s* h, const lbm_axi_launch& c, const std::vector<char>& keep) {
   std::vector<WorkItem> items;
   const int wout = strip_cols(c.width, h->esize);
   for (int k = 0; k < h->n; ++k) {
-    if (only_inst >= 0 && k != only_inst) continue;
+    if (!keep.empty() && !keep[k]) continue;
     const auto& p = h->prm[k];
     const int seg = std::min(c.seg_rows > 0 ? c.seg_rows : p.nr, max_item_rows(row_pitch(p.nz, h->esize), h->esize));
     const int nstrip = std::max(1, (p.nz + wout - 1) / wout);
@@ -264,95 +278,155 @@ lbm_status upload_items(lbm_axi_s* h, const std::vector<WorkItem>& items) {
 }
 
 void drop_graph(lbm_axi_s* h) {
-  if (h->gexec) {
-    (void)hipGraphExecDestroy(h->gexec);
-    h->gexec = nullptr;
-  }
+  for (auto& L : h->grp)
+    for (auto& x : L.gexec)
+      if (x) {
+        (void)hipGraphExecDestroy(x);
+        x = nullptr;
+      }
 }
 
-lbm_status apply_launch(lbm_axi_s* h, const lbm_axi_launch& c) {
+// The group of each instance: largest instances first, each to the group with the fewest
+// nodes so far (every group gets at least one instance when groups <= n).
+std::vector<int> group_of_instances(const lbm_axi_s* h, int groups) {
+  std::vector<int> order(h->n), grp(h->n, 0);
+  for (int k = 0; k < h->n; ++k) order[k] = k;
+  auto nodes = [&](int k) { return (long long)h->prm[k].nz * h->prm[k].nr; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nodes(a) > nodes(b); });
+  long long load[kMaxStreams] = {};
+  for (int k : order) {
+    int g = 0;
+    for (int x = 1; x < groups; ++x)
+      if (load[x] < load[g]) g = x;
+    grp[k] = g;
+    load[g] += nodes(k);
+  }
+  return grp;
+}
+
+lbm_status apply_launch(lbm_axi_s* h, const lbm_axi_launch& c0) {
+  lbm_axi_launch c = c0;
+  if (c.streams == 0) c.streams = 1;
   if (!valid_width(c.width)) return LBM_ERR_UNSUPPORTED;
   if (c.seg_rows != 0 && c.seg_rows < 8) return LBM_ERR_ARG;
   if (c.grid < 0 || (c.regf != 0 && c.regf != 1) || c.xcd_swizzle < 0 || c.xcd_swizzle > 2) return LBM_ERR_ARG;
-  lbm_status s = upload_items(h, build_items(h, c, -1));
+  if (c.streams < 1 || c.streams > kMaxStreams || c.streams > h->n) return LBM_ERR_ARG;
+  for (int g = 1; g < c.streams; ++g) {
+    if (!h->grp[g].st) HIPCHK(hipStreamCreateWithFlags(&h->grp[g].st, hipStreamNonBlocking));
+    if (!h->grp[g].done) HIPCHK(hipEventCreateWithFlags(&h->grp[g].done, hipEventDisableTiming));
+  }
+  if (c.streams > 1 && !h->fork) HIPCHK(hipEventCreateWithFlags(&h->fork, hipEventDisableTiming));
+  const std::vector<int> grp = group_of_instances(h, c.streams);
+  std::vector<WorkItem> all;
+  int first[kMaxStreams] = {}, count[kMaxStreams] = {};
+  for (int g = 0; g < c.streams; ++g) {
+    std::vector<char> keep(h->n);
+    for (int k = 0; k < h->n; ++k) keep[k] = grp[k] == g;
+    const std::vector<WorkItem> items = build_items(h, c, keep);
+    first[g] = (int)all.size();
+    count[g] = (int)items.size();
+    all.insert(all.end(), items.begin(), items.end());
+  }
+  lbm_status s = upload_items(h, all);
   if (s != LBM_OK) return s;
-  h->launch = c;
   drop_graph(h);
-  return LBM_OK;
-}
-
-int grid_of(const lbm_axi_s* h) {
-  if (!h->launch.persistent) return h->n_items;
-  int g = h->launch.grid > 0 ? h->launch.grid : h->cus * (h->launch.width <= 128 ? 8 : 4);
-  return std::max(1, std::min(g, h->n_items));
-}
-
-template <typename R>
-hipError_t enqueue_sweep(lbm_axi_s* h, bool moments, int inst_for_moments, double* mr, double* mz,
-                         double* mu) {
-  SweepArgs<R> g{};
-  g.fin = static_cast<const R*>(h->fbuf[h->cur]);
-  g.fout = static_cast<R*>(h->fbuf[h->cur ^ 1]);
-  g.inst = h->d_inst;
-  g.items = h->d_items;
-  g.n_items = h->n_items;
-  g.xcd_swizzle = h->launch.xcd_swizzle == 1;
-  g.queue = h->d_queue;
-  g.err = h->d_err;
-  g.mrho = mr;
-  g.muz = mz;
-  g.mur = mu;
-  (void)inst_for_moments;
-  return sweep_dispatch<R>(g, h->launch.width, moments, moments ? false : h->launch.persistent != 0,
-                           moments ? false : h->launch.regf != 0, h->any_guo, moments ? h->n_items : grid_of(h),
-                           h->stream);
-}
-
-lbm_status enqueue_steps_eager(lbm_axi_s* h, int64_t nsteps) {
-  for (int64_t s = 0; s < nsteps; ++s) {
-    hipError_t e = h->prec == LBM_PREC_FP32 ? enqueue_sweep<float>(h, false, -1, nullptr, nullptr, nullptr)
-                                            : enqueue_sweep<double>(h, false, -1, nullptr, nullptr, nullptr);
-    if (e != hipSuccess) return LBM_ERR_HIP;
-    h->cur ^= 1;
+  h->launch = c;
+  h->n_groups = c.streams;
+  h->grp[0].st = h->stream;
+  for (int g = 0; g < c.streams; ++g) {
+    h->grp[g].first = first[g];
+    h->grp[g].count = count[g];
   }
   return LBM_OK;
 }
 
-lbm_status capture_graph(lbm_axi_s* h) {
-  drop_graph(h);
+int grid_of(const lbm_axi_s* h, int n_items) {
+  if (!h->launch.persistent) return n_items;
+  int g = h->launch.grid > 0 ? h->launch.grid : h->cus * (h->launch.width <= 128 ? 8 : 4);
+  return std::max(1, std::min(g, n_items));
+}
+
+// One step of group grp from fbuf[cur] into fbuf[cur ^ 1], on the group's stream.
+template <typename R>
+hipError_t enqueue_sweep(lbm_axi_s* h, int grp, int cur) {
+  const auto& L = h->grp[grp];
+  SweepArgs<R> g{};
+  g.fin = static_cast<const R*>(h->fbuf[cur]);
+  g.fout = static_cast<R*>(h->fbuf[cur ^ 1]);
+  g.inst = h->d_inst;
+  g.items = h->d_items + L.first;
+  g.n_items = L.count;
+  g.xcd_swizzle = h->launch.xcd_swizzle == 1;
+  g.queue = h->d_queue + 2 * grp;
+  g.err = h->d_err;
+  return sweep_dispatch<R>(g, h->launch.width, false, h->launch.persistent != 0, h->launch.regf != 0, h->any_guo,
+                           grid_of(h, L.count), L.st);
+}
+
+lbm_status group_steps_eager(lbm_axi_s* h, int grp, int cur, int64_t nsteps) {
+  for (int64_t s = 0; s < nsteps; ++s, cur ^= 1) {
+    hipError_t e = h->prec == LBM_PREC_FP32 ? enqueue_sweep<float>(h, grp, cur) : enqueue_sweep<double>(h, grp, cur);
+    if (e != hipSuccess) return LBM_ERR_HIP;
+  }
+  return LBM_OK;
+}
+
+lbm_status capture_group(lbm_axi_s* h, int grp, int cur) {
+  auto& L = h->grp[grp];
   hipGraph_t graph = nullptr;
-  HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-  const int cur0 = h->cur;
-  lbm_status s = enqueue_steps_eager(h, h->graph_chunk);
-  hipError_t ee = hipStreamEndCapture(h->stream, &graph);
-  h->cur = cur0;  // capture does not run anything; an even chunk returns to the same buffer
+  HIPCHK(hipStreamBeginCapture(L.st, hipStreamCaptureModeThreadLocal));
+  lbm_status s = group_steps_eager(h, grp, cur, h->graph_chunk);
+  hipError_t ee = hipStreamEndCapture(L.st, &graph);
   if (s != LBM_OK) {
     if (graph) (void)hipGraphDestroy(graph);
     return s;
   }
   if (ee != hipSuccess) return LBM_ERR_HIP;
-  hipError_t ie = hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
+  hipError_t ie = hipGraphInstantiate(&L.gexec[cur], graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (ie != hipSuccess) {
-    h->gexec = nullptr;
+    L.gexec[cur] = nullptr;
     return LBM_ERR_HIP;
   }
   return LBM_OK;
 }
 
-lbm_status enqueue_steps(lbm_axi_s* h, int64_t nsteps) {
-  if (h->graph_chunk > 0 && nsteps >= h->graph_chunk) {
-    if (!h->gexec) {
-      lbm_status s = capture_graph(h);
+// nsteps steps of group grp starting from fbuf[cur]: whole graph chunks replayed (a chunk is
+// even, so it ends on the buffer it started from; the graph of each starting buffer is
+// captured when first needed), the rest launched one by one.
+lbm_status group_steps(lbm_axi_s* h, int grp, int cur, int64_t nsteps, bool graphs) {
+  auto& L = h->grp[grp];
+  if (graphs && h->graph_chunk > 0 && nsteps >= h->graph_chunk) {
+    if (!L.gexec[cur]) {
+      lbm_status s = capture_group(h, grp, cur);
       if (s != LBM_OK) return s;
     }
-    while (nsteps >= h->graph_chunk) {
-      HIPCHK(hipGraphLaunch(h->gexec, h->stream));
-      nsteps -= h->graph_chunk;
-    }
+    for (; nsteps >= h->graph_chunk; nsteps -= h->graph_chunk) HIPCHK(hipGraphLaunch(L.gexec[cur], L.st));
   }
-  return enqueue_steps_eager(h, nsteps);
+  return group_steps_eager(h, grp, cur, nsteps);
 }
+
+// nsteps steps of every instance, ordered after earlier work on the handle's stream and
+// before later work on it.
+lbm_status run_steps(lbm_axi_s* h, int64_t nsteps, bool graphs) {
+  if (nsteps == 0) return LBM_OK;
+  const int cur = h->cur;
+  if (h->n_groups > 1) {
+    HIPCHK(hipEventRecord(h->fork, h->stream));
+    for (int g = 1; g < h->n_groups; ++g) HIPCHK(hipStreamWaitEvent(h->grp[g].st, h->fork, 0));
+  }
+  lbm_status st = LBM_OK;
+  for (int g = 0; g < h->n_groups && st == LBM_OK; ++g) st = group_steps(h, g, cur, nsteps, graphs);
+  for (int g = 1; g < h->n_groups; ++g)  // join, also after a failure
+    if (hipEventRecord(h->grp[g].done, h->grp[g].st) != hipSuccess ||
+        hipStreamWaitEvent(h->stream, h->grp[g].done, 0) != hipSuccess)
+      st = LBM_ERR_HIP;
+  if (st == LBM_OK) h->cur = cur ^ (int)(nsteps & 1);
+  return st;
+}
+
+lbm_status enqueue_steps_eager(lbm_axi_s* h, int64_t nsteps) { return run_steps(h, nsteps, false); }
+lbm_status enqueue_steps(lbm_axi_s* h, int64_t nsteps) { return run_steps(h, nsteps, true); }
 
 // The sticky device error bits of the handle (k < 0: any instance) or of instance k.
 lbm_status read_err(lbm_axi_s* h, int k = -1) {
@@ -392,6 +466,12 @@ void free_all(lbm_axi_s* h) {
     if (p) (void)hipFree(p);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
+  for (int g = 1; g < kMaxStreams; ++g) {
+    if (h->grp[g].st) (void)hipStreamSynchronize(h->grp[g].st);
+    if (h->grp[g].st) (void)hipStreamDestroy(h->grp[g].st);
+    if (h->grp[g].done) (void)hipEventDestroy(h->grp[g].done);
+  }
+  if (h->fork) (void)hipEventDestroy(h->fork);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
 
@@ -515,7 +595,8 @@ lbm_status create(int n, const lbm_axi_params* params, int prec, const double* c
   row_start.push_back((int)rows.size());
   h->n_rows = (int)rows.size();
   if (hipMalloc(&h->d_inst, n * sizeof(InstDev)) != hipSuccess ||
-      hipMalloc(&h->d_queue, 2 * sizeof(int)) != hipSuccess || hipMalloc(&h->d_err, (n + 1) * sizeof(int)) != hipSuccess ||
+      hipMalloc(&h->d_queue, 2 * kMaxStreams * sizeof(int)) != hipSuccess ||
+      hipMalloc(&h->d_err, (n + 1) * sizeof(int)) != hipSuccess ||
       hipMalloc(&h->d_rows, rows.size() * sizeof(RowRef)) != hipSuccess ||
       hipMalloc(&h->d_row_start, row_start.size() * sizeof(int)) != hipSuccess ||
       hipMalloc(&h->d_part, rows.size() * 4 * sizeof(double)) != hipSuccess ||
@@ -526,7 +607,8 @@ lbm_status create(int n, const lbm_axi_params* params, int prec, const double* c
       hipMemcpy(h->d_rows, rows.data(), rows.size() * sizeof(RowRef), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(h->d_row_start, row_start.data(), row_start.size() * sizeof(int), hipMemcpyHostToDevice) !=
           hipSuccess ||
-      hipMemset(h->d_queue, 0, 2 * sizeof(int)) != hipSuccess || hipMemset(h->d_err, 0, (n + 1) * sizeof(int)) != hipSuccess)
+      hipMemset(h->d_queue, 0, 2 * kMaxStreams * sizeof(int)) != hipSuccess ||
+      hipMemset(h->d_err, 0, (n + 1) * sizeof(int)) != hipSuccess)
     return fail(LBM_ERR_HIP);
   st = apply_launch(h, default_launch(h));
   if (st != LBM_OK) return fail(st);
@@ -700,7 +782,9 @@ lbm_status lbm_axi_moments(lbm_axi_t h, int32_t k, double* rho, double* uz, doub
   HIPCHK(hipMalloc(&tmp, 3 * n * sizeof(double)));
   // moments of instance k: a work list restricted to it
   const int saved_items = h->n_items;
-  std::vector<WorkItem> items = build_items(h, lbm_axi_launch{h->launch.width, h->launch.seg_rows, 0, 0, 0, 0}, k);
+  std::vector<char> only(h->n, 0);
+  only[k] = 1;
+  std::vector<WorkItem> items = build_items(h, lbm_axi_launch{h->launch.width, h->launch.seg_rows, 0, 0, 0, 0, 1}, only);
   WorkItem* d_items = nullptr;
   lbm_status st = LBM_OK;
   if (hipMalloc(&d_items, items.size() * sizeof(WorkItem)) != hipSuccess) st = LBM_ERR_ALLOC;
@@ -902,14 +986,31 @@ lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch
         // v < 4: bit 0 persistent, bit 1 populations in registers (XCD swizzle);
         // v >= 4: one item per workgroup, longest first, bit 0 populations in registers,
         // bit 1 row bands kept on one XCD
-        const lbm_axi_launch c = v < 4 ? lbm_axi_launch{w, sg, v & 1, 0, 1, v >> 1}
-                                       : lbm_axi_launch{w, sg, 0, 0, v >= 6 ? 2 : 0, v & 1};
+        const lbm_axi_launch c = v < 4 ? lbm_axi_launch{w, sg, v & 1, 0, 1, v >> 1, 1}
+                                       : lbm_axi_launch{w, sg, 0, 0, v >= 6 ? 2 : 0, v & 1, 1};
         double ms = 0.0;
         const lbm_status s = trial(c, steps_per_trial, &ms);
         if (s == LBM_ERR_HIP) st = s;
         if (s == LBM_OK) timed.push_back({ms, c});
       }
   }
+  // Batches: two or three stream groups, which favour shorter segments than one launch
+  // (the tail of one group's step is filled by the others').  One workgroup per item with
+  // row bands on one XCD: persistent grids sized for the whole chip, one per group, measured
+  // twice as slow.
+  const int stream_segs[] = {48, 64, 80, 96, 112};
+  for (int nl = 2; nl <= std::min(3, h->n); ++nl)
+    for (int w : widths) {
+      if (w == 64 || maxnz + 12 <= w / 2) continue;
+      for (int sg : stream_segs)
+        for (int regf = 0; regf < 2 && st == LBM_OK; ++regf) {
+          const lbm_axi_launch c{w, sg, 0, 0, 2, regf, nl};
+          double ms = 0.0;
+          const lbm_status s = trial(c, steps_per_trial, &ms);
+          if (s == LBM_ERR_HIP) st = s;
+          if (s == LBM_OK) timed.push_back({ms, c});
+        }
+    }
   std::sort(timed.begin(), timed.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
   lbm_axi_launch win = keep;
   double win_ms = 1e300;
@@ -927,7 +1028,7 @@ lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch
   lbm_status s2 = apply_launch(h, st == LBM_OK ? win : keep);
   if (st != LBM_OK) return st;
   if (s2 != LBM_OK) return s2;
-  if (best) *best = win;
+  if (best) *best = h->launch;  // as applied (streams = 0 read as 1)
   if (best_ms) *best_ms = win_ms;
   // a failed candidate could have raised the device error word: clear it with the state restored
   HIPCHK(hipMemsetAsync(h->d_err, 0, (h->n + 1) * sizeof(int), h->stream));

@@ -66,7 +66,8 @@ class lbm_axi_params(ctypes.Structure):
 class lbm_axi_launch(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("seg_rows", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("xcd_swizzle", ctypes.c_int32), ("regf", ctypes.c_int32)]
+                ("xcd_swizzle", ctypes.c_int32), ("regf", ctypes.c_int32),
+                ("streams", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

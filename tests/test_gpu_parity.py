@@ -251,6 +251,20 @@ def test_batch_members_equal_single_runs_bitwise():
                 bat.step(60)
                 for k in range(len(ds)):
                     assert np.array_equal(bat.get_f(k), fb[k]), (prec, xs, k)
+        # the members split over two to four stream groups, stepped eagerly and through
+        # graph replays (an odd eager remainder between replays), persistent or not
+        for ns, pers, chunk in ((2, 0, 0), (3, 1, 0), (4, 0, 10), (2, 1, 10)):
+            with L.LbmAxi([gpu_params(d) for d in ds], rhos, precision=prec) as bat:
+                bat.set_launch(width=128, seg_rows=16, persistent=pers, grid=0, xcd_swizzle=2, regf=1,
+                               streams=ns)
+                assert bat.get_launch()["streams"] == ns
+                bat.set_graph_chunk(chunk)
+                for n in (25, 1, 20, 14):
+                    bat.step(n)
+                bat.sync()
+                assert bat.mass().tolist() == mb.tolist(), (prec, ns)
+                for k in range(len(ds)):
+                    assert np.array_equal(bat.get_f(k), fb[k]), (prec, ns, pers, chunk, k)
 
 
 def test_mixed_forcing_batch_equals_single_runs_bitwise():
@@ -268,6 +282,24 @@ def test_mixed_forcing_batch_equals_single_runs_bitwise():
             with L.LbmAxi(gpu_params(d), rhos[k], precision=prec) as one:
                 one.step(50)
                 assert np.array_equal(one.get_f(), fb[k]), (prec, k)
+
+
+def test_graph_replays_after_an_odd_number_of_steps():
+    # A captured chunk reads and writes fixed buffers; after an odd eager remainder the state
+    # sits in the other buffer, so the replays must use the chunk captured from there.
+    L = lbm()
+    d = base(80, 40)
+    rho0 = droplet_rho(d, 12.0, eps=0.1)
+    with L.LbmAxi(gpu_params(d), rho0) as a:
+        a.step(57)
+        ref = a.get_f()
+    with L.LbmAxi(gpu_params(d), rho0) as b:
+        b.set_graph_chunk(10)
+        b.step(13)                  # 1 replay + 3 eager: state in the other buffer
+        b.step(20)                  # 2 replays of the chunk captured from that buffer
+        b.step(11)                  # 1 replay + 1 eager: back to the first buffer
+        b.step(13)
+        assert np.array_equal(b.get_f(), ref)
 
 
 def test_graph_replay_equals_eager_and_repeats():
@@ -387,8 +419,18 @@ def test_host_rejects_bad_input():
     assert e.value.code == -1
     with L.LbmAxi(gpu_params(base(16, 8)), np.full((8, 16), 0.1)) as sim:
         keep = sim.get_launch()
-        for bad_launch in (dict(xcd_swizzle=3), dict(xcd_swizzle=-1), dict(regf=2), dict(seg_rows=5)):
+        for bad_launch in (dict(xcd_swizzle=3), dict(xcd_swizzle=-1), dict(regf=2), dict(seg_rows=5),
+                           dict(streams=2), dict(streams=-1)):
             with pytest.raises(L.LbmError) as e:
                 sim.set_launch(**{**keep, **bad_launch})
             assert e.value.code == -1, bad_launch
         assert sim.get_launch() == keep
+    two = [gpu_params(base(16, 8)), gpu_params(base(24, 8))]
+    with L.LbmAxi(two, [np.full((8, 16), 0.1), np.full((8, 24), 0.1)]) as sim:
+        keep = sim.get_launch()
+        for bad in (3, 5):          # more groups than instances; more than four
+            with pytest.raises(L.LbmError) as e:
+                sim.set_launch(**{**keep, "streams": bad})
+            assert e.value.code == -1, bad
+        sim.set_launch(**{**keep, "streams": 2})
+        assert sim.get_launch()["streams"] == 2
