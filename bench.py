@@ -186,7 +186,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="batch", choices=["batch", "large", "wave", "mode2", "static"])
     ap.add_argument("--precision", default=None, choices=["fp32", "fp64"])
     ap.add_argument("--forms", default="all", choices=["all", "main"],

@@ -179,7 +179,11 @@ lbm_status lbm_axi_sync(lbm_axi_t h);
  * flags is host int32 [n].  Synchronises; the bits stay set (the state is invalid). */
 lbm_status lbm_axi_errors(lbm_axi_t h, int32_t* flags);
 
-/* Replay steps as captured hipGraphs of `chunk` steps (even, >= 2); 0 = eager launches. */
+/* Replay steps as captured hipGraphs of `chunk` steps (even, >= 2); 0 = eager launches.
+ * The chunk starting from the current buffer is captured by this call (nothing runs); the
+ * one starting from the other buffer, when a step first needs it.  A later set_launch
+ * drops the captured chunks (captured again when next needed).  LBM_ERR_ARG for an odd or
+ * negative chunk, LBM_ERR_HIP if the capture fails. */
 lbm_status lbm_axi_set_graph_chunk(lbm_axi_t h, int32_t chunk);
 
 /* ---------------------------------------------------------------- observables (synchronising) */

@@ -391,23 +391,11 @@ lbm_status capture_group(lbm_axi_s* h, int grp, int cur) {
   return LBM_OK;
 }
 
-// nsteps steps of group grp starting from fbuf[cur]: whole graph chunks replayed (a chunk is
-// even, so it ends on the buffer it started from; the graph of each starting buffer is
-// captured when first needed), the rest launched one by one.
-lbm_status group_steps(lbm_axi_s* h, int grp, int cur, int64_t nsteps, bool graphs) {
-  auto& L = h->grp[grp];
-  if (graphs && h->graph_chunk > 0 && nsteps >= h->graph_chunk) {
-    if (!L.gexec[cur]) {
-      lbm_status s = capture_group(h, grp, cur);
-      if (s != LBM_OK) return s;
-    }
-    for (; nsteps >= h->graph_chunk; nsteps -= h->graph_chunk) HIPCHK(hipGraphLaunch(L.gexec[cur], L.st));
-  }
-  return group_steps_eager(h, grp, cur, nsteps);
-}
-
 // nsteps steps of every instance, ordered after earlier work on the handle's stream and
-// before later work on it.
+// before later work on it.  Whole graph chunks are replayed (a chunk is even, so it ends on
+// the buffer it started from; the chunk of each starting buffer is captured when first
+// needed), the rest launched one by one; both go out one step or chunk per group in turn,
+// so that every group's stream has work from the start.
 lbm_status run_steps(lbm_axi_s* h, int64_t nsteps, bool graphs) {
   if (nsteps == 0) return LBM_OK;
   const int cur = h->cur;
@@ -416,7 +404,20 @@ lbm_status run_steps(lbm_axi_s* h, int64_t nsteps, bool graphs) {
     for (int g = 1; g < h->n_groups; ++g) HIPCHK(hipStreamWaitEvent(h->grp[g].st, h->fork, 0));
   }
   lbm_status st = LBM_OK;
-  for (int g = 0; g < h->n_groups && st == LBM_OK; ++g) st = group_steps(h, g, cur, nsteps, graphs);
+  int64_t left = nsteps;
+  if (graphs && h->graph_chunk > 0 && left >= h->graph_chunk) {
+    for (int g = 0; g < h->n_groups && st == LBM_OK; ++g)
+      if (!h->grp[g].gexec[cur]) st = capture_group(h, g, cur);
+    for (; left >= h->graph_chunk && st == LBM_OK; left -= h->graph_chunk)
+      for (int g = 0; g < h->n_groups && st == LBM_OK; ++g)
+        if (hipGraphLaunch(h->grp[g].gexec[cur], h->grp[g].st) != hipSuccess) st = LBM_ERR_HIP;
+  }
+  for (int64_t s = 0; s < left && st == LBM_OK; ++s)
+    for (int g = 0; g < h->n_groups && st == LBM_OK; ++g) {
+      const int c = cur ^ (int)(s & 1);
+      if ((h->prec == LBM_PREC_FP32 ? enqueue_sweep<float>(h, g, c) : enqueue_sweep<double>(h, g, c)) != hipSuccess)
+        st = LBM_ERR_HIP;
+    }
   for (int g = 1; g < h->n_groups; ++g)  // join, also after a failure
     if (hipEventRecord(h->grp[g].done, h->grp[g].st) != hipSuccess ||
         hipStreamWaitEvent(h->stream, h->grp[g].done, 0) != hipSuccess)
@@ -771,6 +772,12 @@ lbm_status lbm_axi_set_graph_chunk(lbm_axi_t h, int32_t chunk) {
   if (!h || chunk < 0 || (chunk > 0 && (chunk < 2 || (chunk & 1)))) return LBM_ERR_ARG;
   drop_graph(h);
   h->graph_chunk = chunk;
+  // capture now, from the buffer the next step starts from, so that the first steps do not
+  // wait for it (the chunk from the other buffer is captured when first needed)
+  for (int g = 0; g < h->n_groups && chunk > 0; ++g) {
+    lbm_status s = capture_group(h, g, h->cur);
+    if (s != LBM_OK) return s;
+  }
   return LBM_OK;
 }
 
@@ -972,8 +979,9 @@ lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch
     if (hipMemcpyAsync(h->fbuf[cur0], save, fb, hipMemcpyDeviceToDevice, h->stream) != hipSuccess) return LBM_ERR_HIP;
     return LBM_OK;
   };
-  // Pass 1: every candidate, steps_per_trial steps.  Pass 2: the four fastest again with
-  // four times the steps, so that run-to-run noise does not pick the winner.
+  // Pass 1: every candidate, steps_per_trial steps.  Pass 2: the four fastest again, twice,
+  // each time with four times the steps and at least ~20 ms of them, so that run-to-run
+  // noise does not pick the winner.
   std::vector<std::pair<double, lbm_axi_launch>> timed;
   int maxnz = 0;
   for (auto& p : h->prm) maxnz = std::max(maxnz, p.nz);
@@ -994,12 +1002,12 @@ lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch
         if (s == LBM_OK) timed.push_back({ms, c});
       }
   }
-  // Batches: two or three stream groups, which favour shorter segments than one launch
-  // (the tail of one group's step is filled by the others').  One workgroup per item with
-  // row bands on one XCD: persistent grids sized for the whole chip, one per group, measured
-  // twice as slow.
+  // Batches: two stream groups, which favour shorter segments than one launch (the tail of
+  // one group's step is filled by the other's).  Three groups run about as fast, four slower;
+  // one workgroup per item with row bands on one XCD: persistent grids sized for the whole
+  // chip, one per group, measured twice as slow.
   const int stream_segs[] = {48, 64, 80, 96, 112};
-  for (int nl = 2; nl <= std::min(3, h->n); ++nl)
+  for (int nl = 2; nl <= std::min(2, h->n); ++nl)
     for (int w : widths) {
       if (w == 64 || maxnz + 12 <= w / 2) continue;
       for (int sg : stream_segs)
@@ -1015,11 +1023,15 @@ lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch
   lbm_axi_launch win = keep;
   double win_ms = 1e300;
   for (size_t i = 0; i < timed.size() && i < 4 && st == LBM_OK; ++i) {
-    double ms = 0.0;
-    st = trial(timed[i].second, 4 * steps_per_trial, &ms);
-    if (st == LBM_OK && ms < win_ms) {
-      win_ms = ms;
-      win = timed[i].second;
+    // at least four times the first pass's steps and about 20 ms of steps, best of two
+    const int steps2 = (int)std::min(200.0, std::max(4.0 * steps_per_trial, std::ceil(20.0 / timed[i].first)));
+    for (int rep = 0; rep < 2 && st == LBM_OK; ++rep) {
+      double ms = 0.0;
+      st = trial(timed[i].second, steps2, &ms);
+      if (st == LBM_OK && ms < win_ms) {
+        win_ms = ms;
+        win = timed[i].second;
+      }
     }
   }
   (void)hipStreamSynchronize(h->stream);
