@@ -32,6 +32,36 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(lbm.EXPORTS)
 
 
+def header_structs():
+    """Field lists (C type, name) of the typedef'd structs the header declares."""
+    text = open(os.path.join(ROOT, "include", "lbm_axi.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef\s+struct\s*\{(.*?)\}\s*(\w+)\s*;", text, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            ctype, names = decl.split(None, 1)
+            fields += [(ctype, n.strip()) for n in names.split(",")]
+        out[name] = fields
+    return out
+
+
+def test_binding_structs_mirror_the_header():
+    # The ctypes structures passed by pointer through the ABI have the header's fields, in
+    # its order and with its types (a missing or reordered field would shift every later one).
+    import ctypes
+    from paper_1512_01977_amd import lbm
+    ctype_of = {"int32_t": ctypes.c_int32, "double": ctypes.c_double}
+    structs = header_structs()
+    for name in ("lbm_axi_params", "lbm_axi_launch"):
+        want = [(n, ctype_of[t]) for t, n in structs[name]]
+        got = [("lambda" if n == "lambda_" else n, t) for n, t in getattr(lbm, name)._fields_]
+        assert got == want, name
+
+
 def test_status_strings():
     from paper_1512_01977_amd import lbm
     L = lbm.lib()
