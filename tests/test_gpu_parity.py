@@ -284,6 +284,30 @@ def test_mixed_forcing_batch_equals_single_runs_bitwise():
                 assert np.array_equal(one.get_f(), fb[k]), (prec, k)
 
 
+def test_autotune_restores_the_state():
+    # The tuner times every candidate shape (stream groups included) on the handle's own
+    # state and restores it after each: after tuning, the state is bitwise the one before,
+    # the error words are clean, and further steps in the chosen shape give bitwise what an
+    # untuned handle gives.
+    L = lbm()
+    ds = [base(64, 32), base(40, 24, tau=0.7, A=-0.1), base(24, 12)]
+    rhos = [droplet_rho(d, 0.3 * d["nr"], eps=0.1, seed=30 + k) for k, d in enumerate(ds)]
+    with L.LbmAxi([gpu_params(d) for d in ds], rhos, precision=1) as ref:
+        ref.step(31)
+        want = [ref.get_f(k) for k in range(len(ds))]
+    with L.LbmAxi([gpu_params(d) for d in ds], rhos, precision=1) as sim:
+        sim.step(11)
+        before = [sim.get_f(k) for k in range(len(ds))]
+        launch, ms = sim.autotune(1)
+        print("tuned", launch, ms, flush=True)
+        assert ms > 0 and sim.get_launch() == launch
+        assert all(np.array_equal(sim.get_f(k), b) for k, b in enumerate(before))
+        assert not sim.errors().any()
+        sim.set_graph_chunk(4)
+        sim.step(20)
+        assert all(np.array_equal(sim.get_f(k), w) for k, w in enumerate(want))
+
+
 def test_graph_replays_after_an_odd_number_of_steps():
     # A captured chunk reads and writes fixed buffers; after an odd eager remainder the state
     # sits in the other buffer, so the replays must use the chunk captured from there.
