@@ -158,3 +158,27 @@ def test_coexistence_zero_crossing():
     assert np.isnan(C.zero_crossing([0.0, 1.0, 2.0], [2.0, np.nan, -1.0]))  # a gap is not bridged
     assert np.isnan(C.zero_crossing([0.0, 1.0], [1.0, 2.0]))
     assert C.zero_crossing([0.0, 1.0], [0.0, 2.0]) == 0.0
+
+
+def test_bench_traffic_belongs_to_its_kernel_and_shape(monkeypatch):
+    # The committed byte counts are used only for the kernel source they were taken on and
+    # only in the launch shape recorded with them (a missing stream count reads as one).
+    import bench
+    rec = bench.traffic_record("droplet_ensemble_256", "f32")
+    assert rec is not None and rec["bytes_per_launch"] > 0 and rec["launch"]
+    shape = dict(rec["launch"])
+    assert bench.same_launch(shape, shape)
+    assert bench.same_launch({k: v for k, v in shape.items() if k != "streams"}, {**shape, "streams": 1})
+    assert bench.same_launch(shape, {**shape, "streams": 1}) == (shape.get("streams", 1) == 1)
+    assert not bench.same_launch(shape, {**shape, "seg_rows": shape["seg_rows"] + 8})
+    assert not bench.same_launch(None, shape)
+    assert bench.traffic_record("no_such_workload", "f32") is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.traffic_record("droplet_ensemble_256", "f32") is None
+
+
+def test_kernel_hash_ignores_comments_and_layout():
+    import bench
+    code = "int f(int x) {  // doubles\n  return 2 * x; /* the value */\n}\n"
+    assert bench.code_text(code) == bench.code_text("int f(int x) {\n\n\treturn 2 * x;\n}")
+    assert bench.code_text(code) != bench.code_text("int f(int x) { return 3 * x; }")
