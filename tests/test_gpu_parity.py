@@ -408,15 +408,21 @@ def test_device_reports_eos_domain_error():
         assert e.value.code in (-4, -5)
 
 
-def test_error_in_one_member_leaves_the_others_readable():
+@pytest.mark.parametrize("streams", [1, 2])
+def test_error_in_one_member_leaves_the_others_readable(streams):
     # A batch of a failing member (as above) and a sound one: the handle-wide sync reports
     # the error, the flags name the failing member only, and the sound member still reads
-    # back bitwise equal to its single-instance run.
+    # back bitwise equal to its single-instance run; also with the two members stepped on
+    # two streams, whose launches share the error words.
     L = lbm()
     bad = base(64, 32, T=0.485 * base(1, 1)["T"] / 0.8, tau=0.8)
     good = base(64, 32)
     rb, rg = droplet_rho(bad, 10.0), droplet_rho(good, 10.0, seed=3)
     with L.LbmAxi([gpu_params(bad), gpu_params(good)], [rb, rg]) as sim:
+        if streams > 1:
+            sim.set_launch(width=128, seg_rows=16, persistent=0, grid=0, xcd_swizzle=2, regf=1,
+                           streams=streams)
+            sim.set_graph_chunk(20)
         sim.step(200)
         with pytest.raises(L.LbmError):
             sim.sync()
