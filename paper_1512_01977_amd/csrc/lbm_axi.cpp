@@ -10,10 +10,9 @@
 
 #include "lbm_axi.h"
 #include "lbm_axi_internal.h"
+#include "work_items.h"
 
 using namespace lbm;
-
-constexpr int kMaxStreams = 4;
 
 struct lbm_axi_s {
   int n = 0;
@@ -156,24 +155,6 @@ InstDev make_inst(const lbm_axi_params& p, long long base, double rho_ref, int e
 
 bool valid_width(int w) { return w == 64 || w == 128 || w == 256; }
 
-// Work-item count and lane-iterations of a launch shape (cost model of the default shape).
-void shape_cost(const lbm_axi_s* h, int width, int seg, long long* items, long long* lane_iters,
-                int* longest) {
-  *items = 0;
-  *lane_iters = 0;
-  *longest = 0;
-  const int wout = strip_cols(width, h->esize);
-  for (const auto& p : h->prm) {
-    const int sg = std::min(seg > 0 ? std::min(seg, p.nr) : p.nr, max_item_rows(row_pitch(p.nz, h->esize), h->esize));
-    const long long nstrip = std::max(1, (p.nz + wout - 1) / wout);
-    const long long nseg = (p.nr + sg - 1) / sg;
-    const int rows = sg + std::min(12, p.nr - sg + 12);  // segment plus its pipeline rows
-    *items += nstrip * nseg;
-    *lane_iters += nstrip * nseg * (long long)width * rows;
-    *longest = std::max(*longest, rows);
-  }
-}
-
 // Default shape without timing anything: minimise max(total lane-iterations / lanes the chip
 // keeps in flight, longest item / 3), the second term being the chain of one work item when
 // the chip is under-filled (its waves then run about three times faster).
@@ -187,7 +168,7 @@ lbm_axi_launch default_launch(const lbm_axi_s* h) {
     for (int sg : segs) {
       long long items, lane_iters;
       int longest;
-      shape_cost(h, w, sg, &items, &lane_iters, &longest);
+      shape_cost(h->prm, (int)h->esize, w, sg, &items, &lane_iters, &longest);
       const double t = std::max((double)lane_iters / cap, longest / 3.0);
       if (t < best_t * 0.999) {
         best_t = t;
@@ -195,71 +176,6 @@ lbm_axi_launch default_launch(const lbm_axi_s* h) {
       }
     }
   return best;
-}
-
-// Reorder a longest-first item list for a launch of one workgroup per item.  The hardware
-// hands workgroup b to XCD b % 8, and each XCD has its own L2.  Neighbouring strips of one
-// row band (same instance, same segment) read each other's edge lines, so the strips of a
-// band go to one XCD, where they run at about the same time and the shared lines come from
-// its L2 instead of HBM.  Bands are dealt in order to the XCD with the most room left; each
-// XCD keeps the list's longest-first order, and XCD x receives exactly the items at
-// positions x, x + 8, ... (a band that does not fit in the room left is split).
-std::vector<WorkItem> deal_over_xcds(const std::vector<WorkItem>& items) {
-  constexpr int kXcd = 8;
-  const size_t n = items.size();
-  std::vector<WorkItem> per[kXcd];
-  size_t room[kXcd];
-  for (int x = 0; x < kXcd; ++x) room[x] = n / kXcd + ((size_t)x < n % kXcd ? 1 : 0);
-  for (size_t i = 0; i < n;) {
-    size_t j = i + 1;
-    while (j < n && items[j].inst == items[i].inst && items[j].s == items[i].s) ++j;
-    while (i < j) {
-      int x = 0;
-      for (int y = 1; y < kXcd; ++y)
-        if (room[y] > room[x]) x = y;
-      const size_t take = std::min(room[x], j - i);
-      per[x].insert(per[x].end(), items.begin() + i, items.begin() + i + take);
-      room[x] -= take;
-      i += take;
-    }
-  }
-  std::vector<WorkItem> out(n);
-  for (int x = 0; x < kXcd; ++x)
-    for (size_t k = 0; k < per[x].size(); ++k) out[k * kXcd + x] = per[x][k];
-  return out;
-}
-
-// Strips of whole 128-byte lines of output columns (at most width - 12) times row
-// segments, for the instances k with keep[k] != 0 (every instance when keep is empty).
-std::vector<WorkItem> build_items(const lbm_axi_s* h, const lbm_axi_launch& c, const std::vector<char>& keep) {
-  std::vector<WorkItem> items;
-  const int wout = strip_cols(c.width, h->esize);
-  for (int k = 0; k < h->n; ++k) {
-    if (!keep.empty() && !keep[k]) continue;
-    const auto& p = h->prm[k];
-    const int seg = std::min(c.seg_rows > 0 ? c.seg_rows : p.nr, max_item_rows(row_pitch(p.nz, h->esize), h->esize));
-    const int nstrip = std::max(1, (p.nz + wout - 1) / wout);
-    for (int s = 0; s < p.nr; s += seg)
-      for (int q = 0; q < nstrip; ++q) {
-        WorkItem w;
-        w.inst = k;
-        w.k0 = q * wout;
-        w.ncols = std::min(wout, p.nz - w.k0);
-        w.s = s;
-        w.e = std::min(p.nr, s + seg);
-        items.push_back(w);
-      }
-  }
-  if (c.persistent || c.xcd_swizzle != 1) {
-    // longest first (rows swept, halo included), so the queue drains evenly; without the
-    // XCD swizzle the hardware deals consecutive workgroups round-robin over the XCDs, so
-    // the same order balances a one-item-per-workgroup launch too
-    auto cost = [](const WorkItem& w) { return (w.e - w.s) + std::min(6, w.s) + 6; };
-    std::stable_sort(items.begin(), items.end(),
-                     [&](const WorkItem& a, const WorkItem& b) { return cost(a) > cost(b); });
-    if (!c.persistent && c.xcd_swizzle == 2) return deal_over_xcds(items);
-  }
-  return items;
 }
 
 lbm_status upload_items(lbm_axi_s* h, const std::vector<WorkItem>& items) {
@@ -286,24 +202,6 @@ void drop_graph(lbm_axi_s* h) {
       }
 }
 
-// The group of each instance: largest instances first, each to the group with the fewest
-// nodes so far (every group gets at least one instance when groups <= n).
-std::vector<int> group_of_instances(const lbm_axi_s* h, int groups) {
-  std::vector<int> order(h->n), grp(h->n, 0);
-  for (int k = 0; k < h->n; ++k) order[k] = k;
-  auto nodes = [&](int k) { return (long long)h->prm[k].nz * h->prm[k].nr; };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nodes(a) > nodes(b); });
-  long long load[kMaxStreams] = {};
-  for (int k : order) {
-    int g = 0;
-    for (int x = 1; x < groups; ++x)
-      if (load[x] < load[g]) g = x;
-    grp[k] = g;
-    load[g] += nodes(k);
-  }
-  return grp;
-}
-
 lbm_status apply_launch(lbm_axi_s* h, const lbm_axi_launch& c0) {
   lbm_axi_launch c = c0;
   if (c.streams == 0) c.streams = 1;
@@ -316,18 +214,8 @@ lbm_status apply_launch(lbm_axi_s* h, const lbm_axi_launch& c0) {
     if (!h->grp[g].done) HIPCHK(hipEventCreateWithFlags(&h->grp[g].done, hipEventDisableTiming));
   }
   if (c.streams > 1 && !h->fork) HIPCHK(hipEventCreateWithFlags(&h->fork, hipEventDisableTiming));
-  const std::vector<int> grp = group_of_instances(h, c.streams);
-  std::vector<WorkItem> all;
   int first[kMaxStreams] = {}, count[kMaxStreams] = {};
-  for (int g = 0; g < c.streams; ++g) {
-    std::vector<char> keep(h->n);
-    for (int k = 0; k < h->n; ++k) keep[k] = grp[k] == g;
-    const std::vector<WorkItem> items = build_items(h, c, keep);
-    first[g] = (int)all.size();
-    count[g] = (int)items.size();
-    all.insert(all.end(), items.begin(), items.end());
-  }
-  lbm_status s = upload_items(h, all);
+  lbm_status s = upload_items(h, launch_items(h->prm, (int)h->esize, c, first, count));
   if (s != LBM_OK) return s;
   drop_graph(h);
   h->launch = c;
@@ -791,7 +679,8 @@ lbm_status lbm_axi_moments(lbm_axi_t h, int32_t k, double* rho, double* uz, doub
   const int saved_items = h->n_items;
   std::vector<char> only(h->n, 0);
   only[k] = 1;
-  std::vector<WorkItem> items = build_items(h, lbm_axi_launch{h->launch.width, h->launch.seg_rows, 0, 0, 0, 0, 1}, only);
+  std::vector<WorkItem> items =
+      build_items(h->prm, (int)h->esize, lbm_axi_launch{h->launch.width, h->launch.seg_rows, 0, 0, 0, 0, 1}, only);
   WorkItem* d_items = nullptr;
   lbm_status st = LBM_OK;
   if (hipMalloc(&d_items, items.size() * sizeof(WorkItem)) != hipSuccess) st = LBM_ERR_ALLOC;
