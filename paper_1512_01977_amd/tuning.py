@@ -1,11 +1,13 @@
 """Launch-shape selection for the fused step kernel.
 
 The library's autotuner (lbm_axi_autotune) times every candidate shape (strip
-width, rows per work item, persistent queue or one workgroup per item) on the
-live state and keeps the fastest.  This module caches its choice per
-architecture, precision and size class in JSON: first the file shipped with the
-package (tuned_launch.json), then a user cache ($LBM_AXI_TUNING_CACHE or
-~/.cache/lbm_axi/tuning.json), so a known size class is not re-tuned.
+width, rows per work item, persistent queue or one workgroup per item in one of
+three orders, populations in registers or gathered again, and for batches two
+stream groups) on the live state and keeps the fastest.  This module caches its
+choice per architecture, precision and size class in JSON: first a file shipped
+with the package (tuned_launch.json, if present), then a user cache
+($LBM_AXI_TUNING_CACHE or ~/.cache/lbm_axi/tuning.json), so a known size class
+is not re-tuned.
 """
 from __future__ import annotations
 
