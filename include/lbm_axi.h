@@ -163,13 +163,17 @@ void lbm_axi_destroy(lbm_axi_t h);
 /* ---------------------------------------------------------------- time stepping */
 
 /* Enqueue nsteps >= 0 time steps of every instance on the handle's stream (Sec. 2:
- * streaming, moments, EOS and psi, F_K + F_axis, h_i, exact-difference BGK).  Returns
+ * streaming, moments, EOS and psi, F_K + F_axis, h_i, exact-difference BGK).  With a
+ * launch shape of several stream groups the steps run on the groups' streams, after the
+ * work already on the handle's stream and before any work enqueued on it later.  Returns
  * before the steps run; LBM_ERR_ARG for a NULL handle or nsteps < 0, LBM_ERR_HIP if a
- * launch fails.  Device-side errors surface at the next synchronising call. */
+ * launch or a graph capture fails.  Device-side errors surface at the next synchronising
+ * call. */
 lbm_status lbm_axi_step(lbm_axi_t h, int64_t nsteps);
 
 /* As lbm_axi_step, then wait; *ms receives the HIP-event time of the launches
- * on the handle's stream (kernel time, no host overhead between steps). */
+ * on the handle's stream (kernel time, no host overhead between steps; with stream
+ * groups, from before the first group's first launch to after the last group's last). */
 lbm_status lbm_axi_step_timed(lbm_axi_t h, int64_t nsteps, double* ms);
 
 /* Wait for the stream and report any device-side error. */
