@@ -3,6 +3,8 @@ parameter objects, and the seeded initial densities (from the input module).
 Holds none of the method's arithmetic."""
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 import oracle as O
@@ -46,3 +48,18 @@ def droplet_rho(d, radius, eps=0.0, noise=1e-4, seed=1, width=5.0, zc=None):
 
 def rel_inf(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def paper_table1():
+    """Table 1 (Sec. 3.1) as printed: {(T, A): (sigma_2D, sigma_axis)}."""
+    out = {}
+    with open(os.path.join(GOLDEN, "table1_surface_tension.txt")) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].split()
+            if line:
+                T, A, s2, sa = map(float, line)
+                out[(T, A)] = (s2, sa)
+    return out

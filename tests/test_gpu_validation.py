@@ -6,6 +6,8 @@ import numpy as np
 import pytest
 from scipy import optimize
 
+from cases import paper_table1
+
 pytestmark = pytest.mark.gpu
 
 
@@ -27,8 +29,8 @@ def r_eq(rho, zc, R, axisym, margin=20):
 
 # --------------------------------------------------------------------------- Table 1
 
-TABLE1 = {(0.9, 0.0): (0.305, 0.304), (0.8, 0.0): (0.928, 0.928),
-          (0.9, -0.152): (0.371, 0.383), (0.8, -0.152): (1.146, 1.158)}
+# the paper's printed values (tests/golden); the T = 0.9 and 0.8 rows are run here
+TABLE1 = {k: v for k, v in paper_table1().items() if k[0] in (0.9, 0.8)}
 
 
 @pytest.mark.parametrize("T,A", sorted(TABLE1))
@@ -144,7 +146,7 @@ def test_mode2_frequency_against_lamb():
     R, rin, rout = r_eq(rho_end, 250.0, 80.0, 1)
     m = t >= 20000
     w_sim = fit_damped_drift(t[m], y[m])[4]
-    w_th = lamb_omega(0.928 * 0.01, R, rin, rout, (0.7 - 0.5) / 3)
+    w_th = lamb_omega(paper_table1()[(0.8, 0.0)][1] * 0.01, R, rin, rout, (0.7 - 0.5) / 3)
     print(f"mode 2: R_eq {R:.2f}, omega_sim {w_sim:.4e}, omega_Lamb {w_th:.4e}, "
           f"relative error {w_sim / w_th - 1:+.3f}", flush=True)
     assert w_sim == pytest.approx(w_th, rel=0.4)
