@@ -447,7 +447,17 @@ def test_host_rejects_bad_input():
     with pytest.raises(L.LbmError) as e:
         L.LbmAxi(gpu_params(base(16, 8, tau=0.4)), np.full((8, 16), 0.1))
     assert e.value.code == -1
+    with pytest.raises(L.LbmError) as e:   # an empty batch
+        L.LbmAxi([], [])
+    assert e.value.code == -1
     with L.LbmAxi(gpu_params(base(16, 8)), np.full((8, 16), 0.1)) as sim:
+        f0 = sim.get_f()
+        sim.step(0)                        # zero steps: nothing runs, the state is unchanged
+        sim.sync()
+        assert np.array_equal(sim.get_f(), f0)
+        with pytest.raises(L.LbmError) as e:
+            sim.step(-1)
+        assert e.value.code == -1
         keep = sim.get_launch()
         for bad_launch in (dict(xcd_swizzle=3), dict(xcd_swizzle=-1), dict(regf=2), dict(seg_rows=5),
                            dict(streams=2), dict(streams=-1)):

@@ -160,6 +160,14 @@ def test_workspace_sizing_and_offset_limit():
     assert ws(1 << 21, 4, lbm.PREC_FP64)[0] == -6      # 22 row blocks of 151 MB exceed 2 GiB
     assert ws(1 << 21, 4, lbm.PREC_FP32)[0] == 0
     assert ws(16384, 3, lbm.PREC_FP32)[0] == -1         # nr < 4
+    assert ws(0, 8, lbm.PREC_FP32)[0] == -1             # nz < 1
+    assert ws(16, 8, 2)[0] == -1                        # unknown precision
+    nb = ctypes.c_size_t()
+    p = (lbm.lbm_axi_params * 1)(lbm.Params(nz=16, nr=8, eos=lbm.EOS_CS, T=0.05).c())
+    assert L.lbm_axi_workspace_bytes(0, p, lbm.PREC_FP32, ctypes.byref(nb)) == -1   # empty batch
+    assert L.lbm_axi_workspace_bytes(1, None, lbm.PREC_FP32, ctypes.byref(nb)) == -1
+    bad_tau = (lbm.lbm_axi_params * 1)(lbm.Params(nz=16, nr=8, tau=0.5, eos=lbm.EOS_CS, T=0.05).c())
+    assert L.lbm_axi_workspace_bytes(1, bad_tau, lbm.PREC_FP32, ctypes.byref(nb)) == -1
 
 
 def test_coexistence_zero_crossing():
