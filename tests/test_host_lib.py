@@ -205,3 +205,40 @@ def test_kernel_hash_ignores_comments_and_layout():
     code = "int f(int x) {  // doubles\n  return 2 * x; /* the value */\n}\n"
     assert bench.code_text(code) == bench.code_text("int f(int x) {\n\n\treturn 2 * x;\n}")
     assert bench.code_text(code) != bench.code_text("int f(int x) { return 3 * x; }")
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # The method's kernel is measured on one GPU; asking for several exits with a message
+    # before anything touches a device.
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_bench_needs_a_gpu():
+    # No CPU fallback: without a visible GPU the benchmark refuses to run.
+    import subprocess
+    import sys
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2 and "needs a GPU" in r.stderr and r.stdout == ""
+
+
+def test_binding_fails_loudly_without_its_library_or_a_gpu(monkeypatch, tmp_path):
+    # No fallback path: a missing library is an error, and so is a handle without a GPU.
+    import numpy as np
+    from paper_1512_01977_amd import lbm
+    monkeypatch.setattr(lbm, "_lib", None)
+    monkeypatch.setattr(lbm, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        lbm.lib()
+    monkeypatch.undo()
+    import torch
+    if not torch.cuda.is_available():
+        with pytest.raises(RuntimeError, match="no GPU"):
+            lbm.LbmAxi(lbm.Params(nz=16, nr=8, eos=lbm.EOS_CS, T=0.05), np.full((8, 16), 0.1))
