@@ -15,7 +15,10 @@
  *    default; Guo's term printed in Sec. 2.1 as the alternative (flag
  *    `forcing`), with its garbled second term read as (c_i.u)(c_i.F)/c_s^4 and
  *    BGK relaxing toward E(rho, u) at the physical velocity u = (j + F/2)/rho.
- *  - h_i (Sec. 2.2) is evaluated from the fields at (x, t).
+ *  - h_i (Sec. 2.2) is evaluated from the fields at (x, t).  Parity unpinned
+ *    for this time centring: the paper gives no scheme for its half-step
+ *    point and prints no value that isolates it (the moments of h_i, which
+ *    do not depend on it, are pinned).
  *  - H_z, H_r (eq. axihz) are node scalars; the stray c_iz, c_ir factors in
  *    the printed equation are dropped, otherwise sum_i h_i would not equal
  *    -rho u_r / r as eq. (masscylinderical) requires.
