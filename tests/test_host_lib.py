@@ -242,3 +242,28 @@ def test_binding_fails_loudly_without_its_library_or_a_gpu(monkeypatch, tmp_path
     if not torch.cuda.is_available():
         with pytest.raises(RuntimeError, match="no GPU"):
             lbm.LbmAxi(lbm.Params(nz=16, nr=8, eos=lbm.EOS_CS, T=0.05), np.full((8, 16), 0.1))
+
+
+def test_committed_traffic_figures_are_consistent():
+    # profiles/traffic.json: the scale factors come from the copy kernel of known size, each
+    # workload's bytes from its counters and those factors, and its algorithmic bytes from
+    # its node count (9 populations read and written, S bytes each).
+    import json
+    d = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    cal = d["calibration"]
+    kib = cal["copy_bytes"] / 1024
+    assert abs(cal["fetch_scale"] - kib / cal["FETCH_SIZE_kib"]) < 1e-12
+    assert abs(cal["write_scale"] - kib / cal["WRITE_SIZE_kib"]) < 1e-12
+    nodes = {"droplet_ensemble_256": 12_889_106, "large_droplet_16384x8192": 16384 * 8192}
+    for key, rec in d.items():
+        if ":" not in key:
+            continue
+        workload, dtype = key.split(":")
+        S = 4 if dtype == "f32" else 8
+        assert rec["algorithmic_bytes_per_launch"] == 2 * 9 * S * nodes[workload]
+        assert abs(rec["read_bytes"] - rec["FETCH_SIZE_kib"] * cal["fetch_scale"] * 1024) < 1.0
+        assert abs(rec["write_bytes"] - rec["WRITE_SIZE_kib"] * cal["write_scale"] * 1024) < 1.0
+        assert abs(rec["bytes_per_launch"] - rec["read_bytes"] - rec["write_bytes"]) < 1.0
+        assert rec["dispatches_per_step"] == rec["launch"].get("streams", 1)
+        # no form reads or writes less than the populations it must move
+        assert rec["read_over_algorithmic"] >= 1.0 and rec["write_over_algorithmic"] >= 1.0
