@@ -7,17 +7,22 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbm_oracle.c")
 LIB = os.path.join(HERE, "liblbm_oracle.so")
+CFLAGS = ["-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+          "-Wall", "-Wextra", "-D_GNU_SOURCE"]
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared",
-           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-           "-D_GNU_SOURCE", SRC, "-o", LIB + ".tmp", "-lm"]
+def compile_source(src: str, lib: str, verbose: bool = False) -> str:
+    """Compile one C source of the oracle into the shared library `lib`."""
+    cmd = ["gcc", *CFLAGS, "-I", HERE, src, "-o", lib + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    return compile_source(SRC, LIB, verbose)
 
 
 if __name__ == "__main__":
