@@ -51,6 +51,7 @@ class _Params(ctypes.Structure):
         ("hr_printed_sign", ctypes.c_int32),
         ("gz", ctypes.c_double),
         ("forcing", ctypes.c_int32),
+        ("source_mid", ctypes.c_int32),
     ]
 
 
@@ -73,11 +74,12 @@ class Params:
     hr_printed_sign: int = 0
     gz: float = 0.0
     forcing: int = 0
+    source_mid: int = 0
 
     def c(self) -> _Params:
         return _Params(self.nz, self.nr, self.tau, self.eos, self.T, self.eos_a, self.eos_b,
                        self.eos_R, self.lam, self.A, self.axisym, self.faxis_sound, self.bc_top,
-                       self.hr_printed_sign, self.gz, self.forcing)
+                       self.hr_printed_sign, self.gz, self.forcing, self.source_mid)
 
 
 _lib = None
@@ -102,6 +104,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_oracle_force_psi.argtypes = [P, dp, dp, dp, dp]
         L.lbm_oracle_source.argtypes = [P] + [ctypes.c_double] * 7 + [dp]
         L.lbm_oracle_source.restype = None
+        L.lbm_oracle_source_field.argtypes = [P, dp, dp, dp, dp]
         L.lbm_oracle_guo_source.argtypes = [ctypes.c_double] * 5 + [dp]
         L.lbm_oracle_guo_source.restype = None
         L.lbm_oracle_threads.argtypes = []
@@ -181,6 +184,17 @@ def force_psi(p: Params, psi: np.ndarray, kappa: np.ndarray | None = None):
 def source(p: Params, r, rho, uz, ur, dr_uz, dz_ur, dr_ur) -> np.ndarray:
     h = np.zeros(9)
     lib().lbm_oracle_source(ctypes.byref(p.c()), r, rho, uz, ur, dr_uz, dz_ur, dr_ur, _ptr(h))
+    return h
+
+
+def source_field(p: Params, rho: np.ndarray, uz: np.ndarray, ur: np.ndarray) -> np.ndarray:
+    """h_i of every node as (9, nr, nz) from node fields rho, u (physical velocity): at the
+    node, or with p.source_mid = 1 the mean over each link's two ends (Sec. 2.2)."""
+    rho, uz, ur = (np.ascontiguousarray(a, dtype=np.float64) for a in (rho, uz, ur))
+    assert rho.shape == uz.shape == ur.shape == (p.nr, p.nz)
+    h = np.zeros((9, p.nr, p.nz))
+    _check(lib().lbm_oracle_source_field(ctypes.byref(p.c()), _ptr(rho), _ptr(uz), _ptr(ur), _ptr(h)),
+           "source_field")
     return h
 
 

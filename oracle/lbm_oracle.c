@@ -15,10 +15,15 @@
  *    default; Guo's term printed in Sec. 2.1 as the alternative (flag
  *    `forcing`), with its garbled second term read as (c_i.u)(c_i.F)/c_s^4 and
  *    BGK relaxing toward E(rho, u) at the physical velocity u = (j + F/2)/rho.
- *  - h_i (Sec. 2.2) is evaluated from the fields at (x, t).  Parity unpinned
- *    for this time centring: the paper gives no scheme for its half-step
- *    point and prints no value that isolates it (the moments of h_i, which
- *    do not depend on it, are pinned).
+ *  - h_i (Sec. 2.2) belongs at the link midpoint (x + c_i/2, t + 1/2); the
+ *    paper gives no discretisation.  Default: evaluated from the fields at
+ *    (x, t).  Flag source_mid = 1: the mean of h_i at the link's two ends x and
+ *    x + c_i, both at time t (second order in space along the link; the half
+ *    time step would need the next step's fields, an implicit scheme), with
+ *    mirrored sources beyond the walls.  Both variants are pinned as
+ *    functions (the moments of h_i; the link average's totals and its order
+ *    of accuracy against h_i at x + c_i/2); which time level the paper meant
+ *    is not fixed by any value it prints.
  *  - H_z, H_r (eq. axihz) are node scalars; the stray c_iz, c_ir factors in
  *    the printed equation are dropped, otherwise sum_i h_i would not equal
  *    -rho u_r / r as eq. (masscylinderical) requires.
@@ -354,6 +359,68 @@ void lbm_oracle_guo_source(double tau, double uz, double ur, double Fz, double F
   }
 }
 
+/* Mirror of direction i across a wall: (c_z, c_r) -> (c_z, -c_r). */
+static int mirror_dir(int i) {
+  for (int q = 0; q < 9; ++q)
+    if (CZ[q] == CZ[i] && CR[q] == -CR[i]) return q;
+  return i;
+}
+
+/* Source of direction i at node (k, j), which may lie one row beyond the axis or the wall:
+ * there it is the source of the mirror node in the mirrored direction, since -rho u_r / r
+ * and H_z are even and H_r is odd under the reflection. */
+static double source_ext(const double* hn, int nz, int nr, int i, int k, int j) {
+  const size_t n = (size_t)nz * nr;
+  k = ((k % nz) + nz) % nz;
+  if (j < 0) return hn[(size_t)mirror_dir(i) * n + at(nz, k, -1 - j)];
+  if (j >= nr) return hn[(size_t)mirror_dir(i) * n + at(nz, k, 2 * nr - 1 - j)];
+  return hn[(size_t)i * n + at(nz, k, j)];
+}
+
+int lbm_oracle_source_field(const lbm_oracle_params* p, const double* rho, const double* uz,
+                            const double* ur, double* h) {
+  if (!p || !rho || !uz || !ur || !h || p->nz < 1 || p->nr < 2) return ERR_ARG;
+  const int nz = p->nz, nr = p->nr;
+  const size_t n = (size_t)nz * nr;
+  if (!p->axisym) {
+    memset(h, 0, 9 * n * sizeof(double));
+    return 0;
+  }
+  double* druz = malloc(n * sizeof(double));
+  double* dzur = malloc(n * sizeof(double));
+  double* drur = malloc(n * sizeof(double));
+  double* hn = p->source_mid ? malloc(9 * n * sizeof(double)) : h;
+  if (!druz || !dzur || !drur || !hn) {
+    free(druz); free(dzur); free(drur);
+    if (hn != h) free(hn);
+    return ERR_ARG;
+  }
+  /* velocity derivatives for H, with the same stencil (Sec. 2.2) */
+  lbm_oracle_derivative(uz, nz, nr, 1, 1.0, top_parity_uz(p), druz);
+  lbm_oracle_derivative(ur, nz, nr, 0, -1.0, -1.0, dzur);
+  lbm_oracle_derivative(ur, nz, nr, 1, -1.0, -1.0, drur);
+#pragma omp parallel for
+  for (int j = 0; j < nr; ++j)
+    for (int k = 0; k < nz; ++k) {
+      size_t x = at(nz, k, j);
+      double hx[9];
+      lbm_oracle_source(p, radius(j), rho[x], uz[x], ur[x], druz[x], dzur[x], drur[x], hx);
+      for (int i = 0; i < 9; ++i) hn[(size_t)i * n + x] = hx[i];
+    }
+  if (p->source_mid) {
+    /* Sec. 2.2: h_i at x + c_i/2, the mean over the link's two ends */
+#pragma omp parallel for
+    for (int j = 0; j < nr; ++j)
+      for (int k = 0; k < nz; ++k)
+        for (int i = 0; i < 9; ++i)
+          h[(size_t)i * n + at(nz, k, j)] =
+              0.5 * (source_ext(hn, nz, nr, i, k, j) + source_ext(hn, nz, nr, i, k + CZ[i], j + CR[i]));
+    free(hn);
+  }
+  free(druz); free(dzur); free(drur);
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Whole step                                                                 */
 /* ------------------------------------------------------------------------ */
@@ -365,6 +432,7 @@ static int check_params(const lbm_oracle_params* p) {
   if (p->eos < ORACLE_EOS_IDEAL || p->eos > ORACLE_EOS_CS) return ERR_ARG;
   if (p->bc_top != ORACLE_TOP_FREE_SLIP && p->bc_top != ORACLE_TOP_NO_SLIP) return ERR_ARG;
   if (p->forcing != ORACLE_FORCING_EDM && p->forcing != ORACLE_FORCING_GUO) return ERR_ARG;
+  if (p->source_mid != 0 && p->source_mid != 1) return ERR_ARG;
   return 0;
 }
 
@@ -445,20 +513,15 @@ static int macro(const lbm_oracle_params* p, const double* f, fields* w) {
   return 0;
 }
 
-/* One time step: collide every node into fs, then stream fs back into f. */
-static int one_step(const lbm_oracle_params* p, double* f, double* fs, fields* w, double* druz,
-                    double* dzur, double* drur) {
+/* One time step: collide every node into fs, then stream fs back into f.  hs: [9][n]
+ * scratch for the source field. */
+static int one_step(const lbm_oracle_params* p, double* f, double* fs, fields* w, double* hs) {
   const int nz = p->nz, nr = p->nr;
   const size_t n = (size_t)nz * nr;
   int e = macro(p, f, w);
   if (e) return e;
-  if (p->axisym) {
-    /* velocity derivatives for H, with the same stencil (Sec. 2.2) */
-    double tz = top_parity_uz(p);
-    lbm_oracle_derivative(w->uz, nz, nr, 1, 1.0, tz, druz);
-    lbm_oracle_derivative(w->ur, nz, nr, 0, -1.0, -1.0, dzur);
-    lbm_oracle_derivative(w->ur, nz, nr, 1, -1.0, -1.0, drur);
-  }
+  e = lbm_oracle_source_field(p, w->rho, w->uz, w->ur, hs);
+  if (e) return e;
   const double omega = 1.0 / p->tau;
 #pragma omp parallel for
   for (int j = 0; j < nr; ++j) {
@@ -466,9 +529,8 @@ static int one_step(const lbm_oracle_params* p, double* f, double* fs, fields* w
       size_t x = at(nz, k, j);
       double rho = w->rho[x];
       double ubz = w->jz[x] / rho, ubr = w->jr[x] / rho;
-      double e0[9], e1[9], h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-      if (p->axisym)
-        lbm_oracle_source(p, radius(j), rho, w->uz[x], w->ur[x], druz[x], dzur[x], drur[x], h);
+      double e0[9], e1[9], h[9];
+      for (int i = 0; i < 9; ++i) h[i] = hs[(size_t)i * n + x];
       if (p->forcing == ORACLE_FORCING_EDM) {
         /* exact-difference method: Delta f_i = E_i(rho, u_b + F dt/rho) - E_i(rho, u_b) */
         lbm_oracle_equilibrium(rho, ubz, ubr, e0);
@@ -548,12 +610,10 @@ int lbm_oracle_step(const lbm_oracle_params* p, double* f, int64_t nsteps) {
   fields w;
   if (fields_alloc(&w, n)) return ERR_ARG;
   double* fs = malloc(9 * n * sizeof(double));
-  double* druz = malloc(n * sizeof(double));
-  double* dzur = malloc(n * sizeof(double));
-  double* drur = malloc(n * sizeof(double));
-  if (!fs || !druz || !dzur || !drur) e = ERR_ARG;
-  for (int64_t s = 0; s < nsteps && !e; ++s) e = one_step(p, f, fs, &w, druz, dzur, drur);
-  free(fs); free(druz); free(dzur); free(drur);
+  double* hs = malloc(9 * n * sizeof(double));
+  if (!fs || !hs) e = ERR_ARG;
+  for (int64_t s = 0; s < nsteps && !e; ++s) e = one_step(p, f, fs, &w, hs);
+  free(fs); free(hs);
   fields_free(&w);
   return e;
 }

@@ -47,6 +47,8 @@ typedef struct {
   int32_t hr_printed_sign; /* 0: H_r with -u_r/r (follows C_r); 1: as printed, +u_r/r */
   double gz;               /* uniform body-force density along z */
   int32_t forcing;         /* ORACLE_FORCING_EDM (Sec. 2.3) or ORACLE_FORCING_GUO (Sec. 2.1) */
+  int32_t source_mid;      /* 0: h_i at the node (x, t); 1: h_i at the link midpoint x + c_i/2,
+                              as the mean of h_i at the link's two ends (Sec. 2.2) */
 } lbm_oracle_params;
 
 /* Equation of state at density rho: pressure P_k, kappa = dP_k/drho and the
@@ -79,6 +81,16 @@ int lbm_oracle_force_psi(const lbm_oracle_params* p, const double* psi, const do
  * velocity u and the three velocity derivatives it needs. */
 void lbm_oracle_source(const lbm_oracle_params* p, double r, double rho, double uz, double ur,
                        double dr_uz, double dz_ur, double dr_ur, double h[9]);
+
+/* The source h_i of every node that one step adds, as [9][nr][nz], from node fields
+ * rho and the physical velocity u (the velocity derivatives are taken here with the
+ * stencil of eq. fifthorderaccuratefinitedifference).  source_mid = 0: h_i(x) of
+ * eq. (axihz) at the node.  source_mid = 1: the evolution equation of Sec. 2.2 evaluates
+ * h_i half-way along the link, at x + c_i/2; here the mean of h_i at x and at x + c_i,
+ * both at time t.  Beyond the axis or the wall, h_i(x + c_i) is that of the mirror node
+ * in the mirrored direction (-rho u_r/r and H_z even, H_r odd).  All zeros in 2-D mode. */
+int lbm_oracle_source_field(const lbm_oracle_params* p, const double* rho, const double* uz,
+                            const double* ur, double* h);
 
 /* Guo's forcing term S_i of Sec. 2.1 at one node: w_i (1 - 1/(2 tau)) [3 (c_i - u).F +
  * 9 (c_i.u)(c_i.F)], u the physical velocity (the printed second term is read as
