@@ -79,6 +79,13 @@ typedef struct {
                                 paper relies on (Sec. 2.3, default), or LBM_FORCING_GUO, the
                                 source term printed in Sec. 2.1 (its second term read as
                                 (c_i.u)(c_i.F)/c_s^4, BGK toward E(rho, u), u = (j + F/2)/rho) */
+  int32_t source_mid;        /* 0: the source h_i of eq. (axihz) from the fields at the node (x, t)
+                                (default); 1: at the link midpoint x + c_i/2 where the evolution
+                                equation of Sec. 2.2 places it, as the mean of h_i at x and at
+                                x + c_i (both at time t; beyond the axis or the wall the mirror
+                                node's source in the mirrored direction).  Launches holding such
+                                an instance run a pipeline one row deeper.  Other values:
+                                LBM_ERR_ARG */
 } lbm_axi_params;
 
 /* Launch shape of the fused step kernel (chosen by lbm_axi_autotune or set by hand). */
@@ -226,7 +233,11 @@ lbm_status lbm_axi_get_launch(lbm_axi_t h, lbm_axi_launch* cfg);
 lbm_status lbm_axi_set_launch(lbm_axi_t h, const lbm_axi_launch* cfg);
 
 /* Time every candidate launch shape for steps_per_trial steps (state saved and
- * restored on the device), keep the fastest, return it and its ms per step. */
+ * restored on the device), keep the fastest, return it and its ms per step.  A handle
+ * whose state has already raised a sticky device error is not tuned: the call returns
+ * that error (LBM_ERR_EOS_DOMAIN / LBM_ERR_NONFINITE) and leaves the error words, the
+ * state and the launch shape as they were.  Synchronising; allocates a copy of one
+ * distribution buffer for the duration of the call. */
 lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch* best,
                             double* best_ms_per_step);
 

@@ -45,6 +45,7 @@ struct lbm_axi_s {
   int cus = 256;
   int graph_chunk = 0;
   bool any_guo = false;  // some instance uses Guo's forcing: launch the kernel that can apply it
+  bool any_mid = false;  // some instance takes its source at the link midpoint: the deeper pipeline
   // Stream groups: with launch.streams > 1 the instances of a batch are split into groups,
   // each stepped by launches of its own on a stream of its own (group 0 on `stream`), so that
   // the last work items of one group's step overlap the next step of the others.  Steps fork
@@ -79,6 +80,7 @@ lbm_status check_params(const lbm_axi_params& p) {
   if (p.axisym != 0 && p.axisym != 1) return LBM_ERR_ARG;
   if (p.faxis_sound != 0 && p.faxis_sound != 1) return LBM_ERR_ARG;
   if (p.forcing != LBM_FORCING_EDM && p.forcing != LBM_FORCING_GUO) return LBM_ERR_ARG;
+  if (p.source_mid != 0 && p.source_mid != 1) return LBM_ERR_ARG;
   if (!std::isfinite(p.A) || !std::isfinite(p.gz) || !std::isfinite(p.T)) return LBM_ERR_ARG;
   return LBM_OK;
 }
@@ -131,6 +133,7 @@ InstDev make_inst(const lbm_axi_params& p, long long base, double rho_ref, int e
   d.faxis_sound = p.faxis_sound;
   d.bc_top = p.bc_top;
   d.forcing = p.forcing;
+  d.source_mid = p.source_mid;
   d.psi_ref2 = d.psi_ref * d.psi_ref;
   if (p.eos == LBM_EOS_CS) {
     d.c1 = p.lambda * p.eos_R * p.T;
@@ -248,7 +251,7 @@ hipError_t enqueue_sweep(lbm_axi_s* h, int grp, int cur) {
   g.queue = h->d_queue + 2 * grp;
   g.err = h->d_err;
   return sweep_dispatch<R>(g, h->launch.width, false, h->launch.persistent != 0, h->launch.regf != 0, h->any_guo,
-                           grid_of(h, L.count), L.st);
+                           h->any_mid, grid_of(h, L.count), L.st);
 }
 
 lbm_status group_steps_eager(lbm_axi_s* h, int grp, int cur, int64_t nsteps) {
@@ -445,6 +448,7 @@ lbm_status create(int n, const lbm_axi_params* params, int prec, const double* c
     h->hinst.push_back(make_inst(params[k], h->base[k], rref, h->esize));
     h->nodes += (long long)params[k].nz * params[k].nr;
     h->any_guo = h->any_guo || params[k].forcing == LBM_FORCING_GUO;
+    h->any_mid = h->any_mid || (params[k].source_mid != 0 && params[k].axisym != 0);
   }
   lbm_status st = LBM_OK;
   auto fail = [&](lbm_status s) {
@@ -521,7 +525,7 @@ hipError_t enqueue_moments(lbm_axi_s* h, int k, double* mr, double* mz, double* 
   g.muz = mz;
   g.mur = mu;
   (void)k;
-  return sweep_dispatch<R>(g, h->launch.width, true, false, false, false, h->n_items, h->stream);
+  return sweep_dispatch<R>(g, h->launch.width, true, false, false, false, false, h->n_items, h->stream);
 }
 
 }  // namespace
@@ -844,6 +848,12 @@ lbm_status lbm_axi_stream_copy(int64_t bytes, int32_t iters, double* gbps) {
 lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch* best, double* best_ms) {
   if (!h || steps_per_trial < 1) return LBM_ERR_ARG;
   HIPCHK(hipStreamSynchronize(h->stream));
+  // A state that has already left the EOS domain (or gone non-finite) is reported, not tuned:
+  // its sticky error words stay as they are.
+  std::vector<int> err_words(h->n + 1, 0);
+  HIPCHK(hipMemcpy(err_words.data(), h->d_err, err_words.size() * sizeof(int), hipMemcpyDeviceToHost));
+  if (err_words[0] & 2) return LBM_ERR_NONFINITE;
+  if (err_words[0] & 1) return LBM_ERR_EOS_DOMAIN;
   const size_t fb = (size_t)h->felems * h->esize;
   void* save = nullptr;
   HIPCHK(hipMalloc(&save, fb));
@@ -927,13 +937,15 @@ lbm_status lbm_axi_autotune(lbm_axi_t h, int32_t steps_per_trial, lbm_axi_launch
   (void)hipFree(save);
   h->graph_chunk = keep_chunk;
   lbm_status s2 = apply_launch(h, st == LBM_OK ? win : keep);
+  // The trials stepped copies of the state, which may have raised error bits that the
+  // restored state does not have: put back the words read before tuning (all clear).
+  if (hipMemcpy(h->d_err, err_words.data(), err_words.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess &&
+      st == LBM_OK)
+    st = LBM_ERR_HIP;
   if (st != LBM_OK) return st;
   if (s2 != LBM_OK) return s2;
   if (best) *best = h->launch;  // as applied (streams = 0 read as 1)
   if (best_ms) *best_ms = win_ms;
-  // a failed candidate could have raised the device error word: clear it with the state restored
-  HIPCHK(hipMemsetAsync(h->d_err, 0, (h->n + 1) * sizeof(int), h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
   return LBM_OK;
 }
 

@@ -20,7 +20,7 @@ struct InstDev {
   int pitch;         // elements of one row of one plane (nz rounded up to 128 bytes); a row
                      // block holds the nine planes' rows: element (i, row, col) at
                      // base + (9 row + i) pitch + col
-  int eos, axisym, faxis_sound, bc_top, forcing;
+  int eos, axisym, faxis_sound, bc_top, forcing, source_mid;
   // EOS in the form the kernels evaluate (FP64 in every precision):
   //   Carnahan-Starling  P = c1 rho n(e) / (1 - e)^3 - c2 rho^2, e = ce rho (c1 = lambda R T, c2 = lambda a, ce = b / 4)
   //   van der Waals      P = c1 rho / (3 - rho) - c2 rho^2       (c1 = 8 lambda T, c2 = 3 lambda)
@@ -48,15 +48,18 @@ struct WorkItem {
 inline int line_elems(int esize) { return 128 / esize; }
 inline int row_pitch(int nz, int esize) { return (nz + line_elems(esize) - 1) / line_elems(esize) * line_elems(esize); }
 inline int strip_cols(int width, int esize) {
-  // output columns of a workgroup of `width` lanes: six halo lanes on either side
-  return (width - 12) / line_elems(esize) * line_elems(esize);
+  // output columns of a workgroup of `width` lanes: six halo lanes on either side (seven
+  // with the link-midpoint source; for every width and element size the whole lines that
+  // fit are the same either way)
+  return (width - 14) / line_elems(esize) * line_elems(esize);
 }
 
-// Rows of one work item of the step kernel (its segment plus 14 rows of pipeline and
-// gather halo) stay within 2 GiB of its load descriptor's base: the segment length cap.
+// Rows of one work item of the step kernel (its segment plus up to 16 rows of pipeline and
+// gather halo: 7 on either side with the link-midpoint source, and the gather's row beyond)
+// stay within 2 GiB of its load descriptor's base: the segment length cap.
 inline int max_item_rows(int pitch, int esize) {
   const long long block = 9LL * pitch * esize;
-  const long long rows = (1LL << 31) / block - 14;
+  const long long rows = (1LL << 31) / block - 16;
   return rows > (1 << 30) ? (1 << 30) : (int)rows;
 }
 
@@ -82,7 +85,7 @@ struct RowRef {
 
 template <typename R>
 hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool persist, bool regf, bool guo,
-                          int grid, hipStream_t st);
+                          bool mid, int grid, hipStream_t st);
 template <typename R>
 hipError_t launch_unstream(R* fout, int nz, int pitch, int nr, int bc_top, double rho_ref,
                            const double* rho0,

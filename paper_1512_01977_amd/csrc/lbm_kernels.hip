@@ -366,19 +366,26 @@ __device__ __forceinline__ float psi_shifted(double psi2, double psi_ref, double
   return num * recip(__builtin_fmaxf(den, 1e-30f));
 }
 
-// REGF: carry the populations gathered in stage A for six rows in registers instead of
-// gathering them again in stage D (fewer loads that miss L2, more registers).
-template <typename R, int W, bool MOMENTS, bool REGF, bool GUO>
-__device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem wi, char* lds, int lane) {
+// REGF: carry the populations gathered in stage A in registers until the collision instead
+// of gathering them again there (fewer loads that miss L2, more registers).
+// MID: some instance takes the source h_i at the link midpoint x + c_i/2 (Sec. 2.2) as the
+// mean of h_i at the link's two ends: stage D then only forms m0 = -rho u_r / r and 3H of
+// its row into a three-row LDS ring, and a fifth stage E collides the row below it with the
+// per-direction means (ghost rows across the axis and the wall hold the mirror values:
+// m0 and H_z even, H_r odd).  That adds a row to the pipeline and a column to the halo.
+template <typename R, int W, bool MOMENTS, bool REGF, bool GUO, bool MID>
+__device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem wi, char* lds, R* hring, int lane) {
+  constexpr int HALO = MID ? 7 : 6;  // columns of halo on either side of the output strip
+  constexpr int LAG = MID ? 7 : 6;   // rows from the gather to the collision
   const InstDev I = g.inst[wi.inst];
   const int nz = I.nz, nr = I.nr;
   // lanes past the right halo feed nothing: they gather the last halo lane's column (the
   // same lines), so they add no memory traffic
-  const unsigned col = (unsigned)wrapi(wi.k0 - 6 + min(lane, wi.ncols + 11), nz);
+  const unsigned col = (unsigned)wrapi(wi.k0 - HALO + min(lane, wi.ncols + 2 * HALO - 1), nz);
   const unsigned cm = (unsigned)wrapi((int)col - 1, nz), cp = (unsigned)wrapi((int)col + 1, nz);
-  const bool out_lane = lane >= 6 && lane < 6 + wi.ncols;
+  const bool out_lane = lane >= HALO && lane < HALO + wi.ncols;
   const int s = wi.s, e = wi.e;
-  const int a_lo = max(0, s - 6), a_hi = min(nr, e + 6);
+  const int a_lo = max(0, s - LAG), a_hi = min(nr, e + LAG);
   // gathers touch rows a_lo - 1 .. a_hi: the load descriptor is based at row block x0
   const int x0 = max(0, a_lo - 1);
   const long long rs = 9LL * I.pitch;  // elements between row blocks
@@ -389,19 +396,22 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
   const unsigned bcol = col * (unsigned)sizeof(R), bm = cm * (unsigned)sizeof(R), bp = cp * (unsigned)sizeof(R);
   // The strip that ends a row also fills the row's padding (columns nz .. pitch - 1, never
   // read) from its first halo lanes, so that the row's last line is written whole.
-  const int ucol = wi.k0 - 6 + lane;
+  const int ucol = wi.k0 - HALO + lane;
   const bool pad_lane = wi.k0 + wi.ncols == nz && ucol >= nz && ucol < I.pitch;
   const unsigned bst = pad_lane ? (unsigned)ucol * (unsigned)sizeof(R) : bcol;
   // Other halo lanes (and idle pipeline steps) issue the same stores at an offset past the
   // store descriptor's range, which the hardware drops: every wave then issues the same
   // store sequence, which keeps the compiler's wait counts exact, without writing anything.
   constexpr unsigned kDrop = 0x80000000u;
-  const int b_lo = max(0, s - 4), b_hi = min(nr, e + 4);
-  const int c_lo = max(0, s - 2), c_hi = min(nr, e + 2);
+  const int b_lo = max(0, s - LAG + 2), b_hi = min(nr, e + LAG - 2);
+  const int c_lo = max(0, s - LAG + 4), c_hi = min(nr, e + LAG - 4);
+  const int d_lo = max(0, s - 1), d_hi = min(nr, e + 1);  // rows of the source ring (MID)
   const R omega = R(I.omega), nu = R(I.nu), gzf = R(I.gz), rho_ref = R(I.rho_ref);
   const R A6 = R(6.0 * I.A), B6 = R(6.0 * (1.0 - 2.0 * I.A));
   const R top_uz = I.bc_top == LBM_TOP_NO_SLIP ? R(-1) : R(1);
   const R psi_ref = R(I.psi_ref), pr2 = R(2.0 * I.psi_ref);
+  const bool guo = GUO && I.forcing == LBM_FORCING_GUO;
+  const bool mid = MID && I.source_mid != 0;
   const Rings<R, W> L{lds};
   constexpr int ROWB = Rings<R, W>::ROWB;
   constexpr R i36 = R(1.0 / 36.0);
@@ -414,20 +424,23 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
 #pragma unroll
   for (int k = 0; k < 5; ++k) rb[k] = lane_off + slot(a_lo - k) * ROWB;
 
-  // node values travelling from stage A to stage C (age 4) and D (age 6), and from B/C onward
-  R sg_d[7], jz_d[7], jr_d[7], kap_d[5];
+  // node values travelling from stage A to stage C (age 4) and to the collision (age LAG),
+  // and from B/C onward
+  R sg_d[LAG + 1], jz_d[LAG + 1], jr_d[LAG + 1], kap_d[5];
 #pragma unroll
-  for (int q = 0; q < 7; ++q) sg_d[q] = jz_d[q] = jr_d[q] = R(0);
+  for (int q = 0; q <= LAG; ++q) sg_d[q] = jz_d[q] = jr_d[q] = R(0);
 #pragma unroll
   for (int q = 0; q < 5; ++q) kap_d[q] = R(0);
   R fk0z = 0, fk0r = 0, fk1z = 0, fk1r = 0, fk2z = 0, fk2r = 0;
-  R fc0z = 0, fc0r = 0, fc1z = 0, fc1r = 0, fc2z = 0, fc2r = 0;
+  R fcz[LAG - 3], fcr[LAG - 3];  // F of the stage-C row, carried to the collision
+#pragma unroll
+  for (int q = 0; q < LAG - 3; ++q) fcz[q] = fcr[q] = R(0);
   R ir0 = 0, ir1 = 0, ir2 = 0;  // 1/r of the stage-C row, two iterations deep
   int bad = 0;
 
-  R fd[REGF ? 7 : 1][9];  // populations of rows t .. t-6 (REGF only)
+  R fd[REGF ? LAG + 1 : 1][9];  // populations of rows t .. t - LAG (REGF only)
 #pragma unroll
-  for (int a = 0; a < (REGF ? 7 : 1); ++a)
+  for (int a = 0; a < (REGF ? LAG + 1 : 1); ++a)
 #pragma unroll
     for (int i = 0; i < 9; ++i) fd[a][i] = R(0);
 
@@ -439,15 +452,52 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
     for (int i = 0; i < 9; ++i) bstore(__builtin_nondeterministic_value(R(0)), pout.g, kDrop, i * pout.pstride);
   }
 
-  for (int t = a_lo; t < e + 6; ++t) {
+  // Populations of row x for its collision: carried in registers (REGF) or the row gathered
+  // one collision ahead, whose successor is gathered now.
+  auto take_f = [&](int x, R f[9]) {
+    if (x < s || x >= e) return;
     if (REGF) {
 #pragma unroll
-      for (int a = 6; a > 0; --a)
+      for (int i = 0; i < 9; ++i) f[i] = fd[REGF ? LAG : 0][i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = fg[i];
+      if (x + 1 < e) gather_row<R>(pin, nr, I.bc_top, x + 1, x0, bm, bcol, bp, fg);
+    }
+  };
+  // Collision of row x (eq. lbm) and the nine stores of its populations; h_i enters through
+  // m0 and 3H (node source), or per direction through hmid (link-midpoint source, MID).
+  auto collide_store = [&](int x, const R f[9], R m0, R H3z, R H3r, const R* hmid) {
+    const bool active = x >= s && x < e;
+    R o[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) o[i] = __builtin_nondeterministic_value(R(0));
+    if (active) {
+      const R sg = sg_d[LAG], jz = jz_d[LAG], jr = jr_d[LAG];
+      const R rho = rho_ref + sg;
+      collide<R>(f, rho, sg, jz, jr, fcz[LAG - 4], fcr[LAG - 4], m0, H3z, H3r, omega, guo, o);
+      if (MID && hmid) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) o[i] += hmid[i];
+      }
+    }
+    // Every iteration issues the same nine stores (dropped while the stage idles and for
+    // halo lanes), which lets the compiler keep the prefetched loads in flight.
+    const unsigned orow = active ? (unsigned)(x - x0) * pout.rstride : 0u;
+    const unsigned voff = active && (out_lane || pad_lane) ? bst : kDrop;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) bstore(o[i], pout.g, voff, orow + i * pout.pstride);
+  };
+
+  for (int t = a_lo; t < e + LAG; ++t) {
+    if (REGF) {
+#pragma unroll
+      for (int a = LAG; a > 0; --a)
 #pragma unroll
         for (int i = 0; i < 9; ++i) fd[REGF ? a : 0][i] = fd[REGF ? a - 1 : 0][i];
     }
 #pragma unroll
-    for (int q = 6; q > 0; --q) {
+    for (int q = LAG; q > 0; --q) {
       sg_d[q] = sg_d[q - 1];
       jz_d[q] = jz_d[q - 1];
       jr_d[q] = jr_d[q - 1];
@@ -455,9 +505,12 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
 #pragma unroll
     for (int q = 4; q > 0; --q) kap_d[q] = kap_d[q - 1];
     fk2z = fk1z; fk2r = fk1r; fk1z = fk0z; fk1r = fk0r;
-    fc2z = fc1z; fc2r = fc1r; fc1z = fc0z; fc1r = fc0r;
+#pragma unroll
+    for (int q = LAG - 4; q > 0; --q) {
+      fcz[q] = fcz[q - 1];
+      fcr[q] = fcr[q - 1];
+    }
     ir2 = ir1; ir1 = ir0;
-
     // ------------------------------------------------------------------ A: row t (slot rb[0])
     {
       const int x = t;
@@ -552,8 +605,8 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         const R irho = recip(rho);
         const R uz = fmad(R(0.5), fz, jz) * irho;
         const R ur = fmad(R(0.5), fr, jr) * irho;
-        fc0z = fz;
-        fc0r = fr;
+        fcz[0] = fz;
+        fcr[0] = fr;
         L.at(R_UZ, r.s0, 0) = uz;
         L.at(R_UR, r.s0, 0) = ur;
         if (x == 0) { L.at(R_UZ, rb[0], 0) = uz; L.at(R_UR, rb[0], 0) = -ur; }  // row -1 = row t - 5
@@ -577,46 +630,72 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
     // ------------------------------------------------------------------ D: row t-6 (rows t-8 .. t-4)
     if (!MOMENTS) {
       const int x = t - 6;
-      const bool active = x >= s && x < e;
-      R o[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) o[i] = __builtin_nondeterministic_value(R(0));
-      if (active) {
+      // H of eq. (axihz) from the velocity ring; H_r carries -u_r/r so that sum_i c_ir h_i
+      // supplies C_r = 2 mu d/dr(u_r/r)
+      R m0 = R(0), H3z = R(0), H3r = R(0);
+      const bool hrow = MID ? (x >= d_lo && x < d_hi) : (x >= s && x < e);
+      R f[9];
+      if (!MID) take_f(x, f);
+      if (I.axisym && hrow) {
         const Rows5 r{rb[3], rb[2], rb[1], rb[0], rb[4]};
-        R f[9];
-        if (REGF) {
-#pragma unroll
-          for (int i = 0; i < 9; ++i) f[i] = fd[REGF ? 6 : 0][i];
-        } else {
-#pragma unroll
-          for (int i = 0; i < 9; ++i) f[i] = fg[i];
-          if (x + 1 < e) gather_row<R>(pin, nr, I.bc_top, x + 1, x0, bm, bcol, bp, fg);
-        }
-        const R sg = sg_d[6], jz = jz_d[6], jr = jr_d[6];
-        const R rho = rho_ref + sg;
-        R m0 = R(0), H3z = R(0), H3r = R(0);
-        if (I.axisym) {
-          // eq. (axihz); H_r carries -u_r/r so that sum_i c_ir h_i supplies C_r = 2 mu d/dr(u_r/r)
-          const R uz = L.at(R_UZ, r.s0, 0), ur = L.at(R_UR, r.s0, 0);
-          const R druz = stencil_dr36<R, W>(L, R_UZ, r);  // 36 D_r u_z
-          const R dzur = stencil_dz36<R, W>(L, R_UR, r);  // 36 D_z u_r
-          const R drur = stencil_dr36<R, W>(L, R_UR, r);  // 36 D_r u_r
-          const R ir = ir2;
-          const R mu36 = rho * nu * i36;
-          const R ir3 = R(3) * ir;
-          const R rur = rho * ur;
-          H3z = fmad(mu36, druz + dzur, -rur * uz) * ir3;
-          H3r = fmad(R(2) * mu36, fmad(R(-36) * ur, ir, drur), -rur * ur) * ir3;
-          m0 = -rur * ir;
-        }
-        collide<R>(f, rho, sg, jz, jr, fc2z, fc2r, m0, H3z, H3r, omega, GUO && I.forcing == LBM_FORCING_GUO, o);
+        const R rho = rho_ref + sg_d[6];
+        const R uz = L.at(R_UZ, r.s0, 0), ur = L.at(R_UR, r.s0, 0);
+        const R druz = stencil_dr36<R, W>(L, R_UZ, r);  // 36 D_r u_z
+        const R dzur = stencil_dz36<R, W>(L, R_UR, r);  // 36 D_z u_r
+        const R drur = stencil_dr36<R, W>(L, R_UR, r);  // 36 D_r u_r
+        const R ir = ir2;
+        const R mu36 = rho * nu * i36;
+        const R ir3 = R(3) * ir;
+        const R rur = rho * ur;
+        H3z = fmad(mu36, druz + dzur, -rur * uz) * ir3;
+        H3r = fmad(R(2) * mu36, fmad(R(-36) * ur, ir, drur), -rur * ur) * ir3;
+        m0 = -rur * ir;
       }
-      // Every iteration issues the same nine stores (dropped while the stage idles and for
-      // halo lanes), which lets the compiler keep the prefetched loads in flight.
-      const unsigned orow = active ? (unsigned)(x - x0) * pout.rstride : 0u;
-      const unsigned voff = active && (out_lane || pad_lane) ? bst : kDrop;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) bstore(o[i], pout.g, voff, orow + i * pout.pstride);
+      if (!MID) {
+        collide_store(x, f, m0, H3z, H3r, nullptr);
+      } else {
+        // the source ring: element (row slot, column, field), fields m0, 3H_z, 3H_r; the
+        // row below the axis and the row beyond the wall hold the mirror values
+        auto H = [&](int row, int dz, int q) -> R& {
+          return hring[((wrapi(row, 3) * (W + 2)) + lane + 1 + dz) * 3 + q];
+        };
+        if (hrow) {
+          H(x, 0, 0) = m0;
+          H(x, 0, 1) = H3z;
+          H(x, 0, 2) = H3r;
+          if (x == 0) { H(-1, 0, 0) = m0; H(-1, 0, 1) = H3z; H(-1, 0, 2) = -H3r; }
+        } else if (d_hi == nr && x == nr) {
+          H(nr, 0, 0) = H(nr - 1, 0, 0);
+          H(nr, 0, 1) = H(nr - 1, 0, 1);
+          H(nr, 0, 2) = -H(nr - 1, 0, 2);
+        }
+        lds_barrier();
+        // ---------------------------------------------------------------- E: row t-7 (rows t-8 .. t-6)
+        const int xe = t - 7;
+        take_f(xe, f);
+        if (!mid) {
+          collide_store(xe, f, H(xe, 0, 0), H(xe, 0, 1), H(xe, 0, 2), nullptr);
+        } else {
+          // h_i(x + c_i/2) = (h_i(x) + h_i(x + c_i)) / 2, h_i = w_i (m0 + c_iz 3H_z + c_ir 3H_r)
+          const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 18.0), w2 = R(1.0 / 72.0);  // w_i / 2 for i > 0
+          const R a0 = H(xe, 0, 0), az = H(xe, 0, 1), ar = H(xe, 0, 2);
+          auto link = [&](int dr, int dz, R wh, int cz, int cr) {
+            const R b0 = H(xe + dr, dz, 0), bz = H(xe + dr, dz, 1), bhr = H(xe + dr, dz, 2);
+            return wh * ((a0 + b0) + R(cz) * (az + bz) + R(cr) * (ar + bhr));
+          };
+          R hm[9];
+          hm[0] = w0 * a0;
+          hm[1] = link(0, 1, w1, 1, 0);
+          hm[2] = link(1, 0, w1, 0, 1);
+          hm[3] = link(0, -1, w1, -1, 0);
+          hm[4] = link(-1, 0, w1, 0, -1);
+          hm[5] = link(1, 1, w2, 1, 1);
+          hm[6] = link(1, -1, w2, -1, 1);
+          hm[7] = link(-1, -1, w2, -1, -1);
+          hm[8] = link(-1, 1, w2, 1, -1);
+          collide_store(xe, f, R(0), R(0), R(0), hm);
+        }
+      }
     }
     {  // row t + 1 takes the slot of row t - 4
       const int r4 = rb[4];
@@ -645,18 +724,24 @@ __device__ __forceinline__ int xcd_map(int b, int G) {
 // vector memory counter and would make the wave wait for its prefetched rows.  The
 // persistent loop keeps more state live and the variants that carry the populations in
 // registers need more; they get one wave less, or take what they need.
-template <typename R, bool PERSIST, bool REGF>
+// The link-midpoint source (MID) keeps more values live: three waves in FP32 and two in
+// FP64 when gathering again, two and one with the populations in registers.
+template <typename R, bool PERSIST, bool REGF, bool MID>
 struct SweepWaves {
   static constexpr int base = REGF ? (sizeof(R) == 4 ? 3 : 1) : (sizeof(R) == 4 ? 4 : 2);
-  static constexpr int value = (PERSIST && !REGF) ? base - 1 : base;
+  static constexpr int mid = REGF ? (sizeof(R) == 4 ? 2 : 1) : (sizeof(R) == 4 ? 3 : 2);
+  static constexpr int value = MID ? mid : (PERSIST && !REGF) ? base - 1 : base;
 };
 
 // GUO: some instance of the launch uses Guo's forcing (a per-instance branch); otherwise
-// only the exact-difference collision is compiled in.
-template <typename R, int W, bool MOMENTS, bool PERSIST, bool REGF, bool GUO>
-__global__ void __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(SweepWaves<R, PERSIST, REGF>::value)))
-k_sweep(SweepArgs<R> g) {
+// only the exact-difference collision is compiled in.  MID: some instance takes its source
+// at the link midpoint (the deeper pipeline of run_item); otherwise the node source only.
+template <typename R, int W, bool MOMENTS, bool PERSIST, bool REGF, bool GUO, bool MID>
+__global__ void __launch_bounds__(W)
+__attribute__((amdgpu_waves_per_eu(SweepWaves<R, PERSIST, REGF, MID>::value))) k_sweep(SweepArgs<R> g) {
+  constexpr int HALO = MID ? 7 : 6;
   __shared__ R ring[RD][W + 4][NRING];
+  __shared__ R hring[MID ? 3 * (W + 2) * 3 : 1];
   __shared__ int s_ticket;
   const int lane = threadIdx.x;
   char* const lds = reinterpret_cast<char*>(&ring[0][0][0]);
@@ -665,15 +750,16 @@ k_sweep(SweepArgs<R> g) {
     const int item = g.xcd_swizzle ? xcd_map(b, (int)gridDim.x) : b;
     if (item >= g.n_items) return;
     const WorkItem wi = g.items[item];
-    // Only lanes 0 .. ncols + 11 (the output columns and six halo columns on either side)
-    // feed an output, and at the end of a row the lanes that fill its padding store.  A wave
-    // with none of them ends here, which frees its SIMD slot for other workgroups (narrow
+    // Only lanes 0 .. ncols + 2 HALO - 1 (the output columns and the halo columns on either
+    // side) feed an output, and at the end of a row the lanes that fill its padding store.  A
+    // wave with none of them ends here, which frees its SIMD slot for other workgroups (narrow
     // members of a batch, the last strip of a row); s_barrier waits only for the waves of
     // the group still running.
     const InstDev* ip = g.inst + wi.inst;
-    const int need = wi.k0 + wi.ncols == ip->nz ? max(wi.ncols + 12, ip->pitch - wi.k0 + 6) : wi.ncols + 12;
+    const int need = wi.k0 + wi.ncols == ip->nz ? max(wi.ncols + 2 * HALO, ip->pitch - wi.k0 + HALO)
+                                                : wi.ncols + 2 * HALO;
     if (__builtin_amdgcn_readfirstlane(lane >> 6) * 64 >= need) return;
-    run_item<R, W, MOMENTS, REGF, GUO>(g, wi, lds, lane);
+    run_item<R, W, MOMENTS, REGF, GUO, MID>(g, wi, lds, hring, lane);
     return;
   }
   for (;;) {
@@ -682,7 +768,7 @@ k_sweep(SweepArgs<R> g) {
     const int item = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform across the workgroup
     lds_barrier();
     if (item >= g.n_items) break;
-    run_item<R, W, MOMENTS, REGF, GUO>(g, g.items[item], lds, lane);
+    run_item<R, W, MOMENTS, REGF, GUO, MID>(g, g.items[item], lds, hring, lane);
   }
   if (lane == 0) {
     // The last workgroup out rewinds the queue for the next launch (no memset needed,
@@ -916,29 +1002,31 @@ hipError_t launch_copy(const void* src, void* dst, long long bytes, hipStream_t 
 
 // ---------------------------------------------------------------------------- host-side launchers
 
-template <typename R, int W, bool MOMENTS, bool PERSIST, bool REGF, bool GUO>
+template <typename R, int W, bool MOMENTS, bool PERSIST, bool REGF, bool GUO, bool MID>
 static hipError_t launch_sweep(const SweepArgs<R>& g, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_sweep<R, W, MOMENTS, PERSIST, REGF, GUO>), dim3(grid), dim3(W), 0, st, g);
+  hipLaunchKernelGGL((k_sweep<R, W, MOMENTS, PERSIST, REGF, GUO, MID>), dim3(grid), dim3(W), 0, st, g);
   return hipGetLastError();
 }
 
-template <typename R, int W, bool GUO>
+template <typename R, int W, bool GUO, bool MID>
 static hipError_t launch_step(const SweepArgs<R>& g, bool persist, bool regf, int grid, hipStream_t st) {
   if (persist)
-    return regf ? launch_sweep<R, W, false, true, true, GUO>(g, grid, st)
-                : launch_sweep<R, W, false, true, false, GUO>(g, grid, st);
-  return regf ? launch_sweep<R, W, false, false, true, GUO>(g, grid, st)
-              : launch_sweep<R, W, false, false, false, GUO>(g, grid, st);
+    return regf ? launch_sweep<R, W, false, true, true, GUO, MID>(g, grid, st)
+                : launch_sweep<R, W, false, true, false, GUO, MID>(g, grid, st);
+  return regf ? launch_sweep<R, W, false, false, true, GUO, MID>(g, grid, st)
+              : launch_sweep<R, W, false, false, false, GUO, MID>(g, grid, st);
 }
 
+// The link-midpoint kernels carry Guo's per-instance branch too (one instantiation for both).
 template <typename R>
 hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool persist, bool regf, bool guo,
-                          int grid, hipStream_t st) {
+                          bool mid, int grid, hipStream_t st) {
 #define LBM_CASE(WW)                                                                                \
   case WW:                                                                                          \
-    if (moments) return launch_sweep<R, WW, true, false, false, false>(g, grid, st);                \
-    return guo ? launch_step<R, WW, true>(g, persist, regf, grid, st)                               \
-               : launch_step<R, WW, false>(g, persist, regf, grid, st);
+    if (moments) return launch_sweep<R, WW, true, false, false, false, false>(g, grid, st);         \
+    if (mid) return launch_step<R, WW, true, true>(g, persist, regf, grid, st);                     \
+    return guo ? launch_step<R, WW, true, false>(g, persist, regf, grid, st)                        \
+               : launch_step<R, WW, false, false>(g, persist, regf, grid, st);
   switch (width) {
     LBM_CASE(64)
     LBM_CASE(128)
@@ -950,8 +1038,9 @@ hipError_t sweep_dispatch(const SweepArgs<R>& g, int width, bool moments, bool p
   return hipErrorInvalidValue;
 }
 
-template hipError_t sweep_dispatch<float>(const SweepArgs<float>&, int, bool, bool, bool, bool, int, hipStream_t);
-template hipError_t sweep_dispatch<double>(const SweepArgs<double>&, int, bool, bool, bool, bool, int,
+template hipError_t sweep_dispatch<float>(const SweepArgs<float>&, int, bool, bool, bool, bool, bool, int,
+                                          hipStream_t);
+template hipError_t sweep_dispatch<double>(const SweepArgs<double>&, int, bool, bool, bool, bool, bool, int,
                                            hipStream_t);
 
 template <typename R>

@@ -60,6 +60,7 @@ class lbm_axi_params(ctypes.Structure):
         ("bc_top", ctypes.c_int32),
         ("gz", ctypes.c_double),
         ("forcing", ctypes.c_int32),
+        ("source_mid", ctypes.c_int32),
     ]
 
 
@@ -91,11 +92,12 @@ class Params:
     bc_top: int = TOP_FREE_SLIP
     gz: float = 0.0
     forcing: int = 0
+    source_mid: int = 0
 
     def c(self) -> lbm_axi_params:
         return lbm_axi_params(self.nz, self.nr, self.tau, self.eos, self.T, self.eos_a, self.eos_b,
                               self.eos_R, self.lam, self.A, self.axisym, self.faxis_sound,
-                              self.bc_top, self.gz, self.forcing)
+                              self.bc_top, self.gz, self.forcing, self.source_mid)
 
 
 _lib = None

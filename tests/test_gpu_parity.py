@@ -408,6 +408,27 @@ def test_device_reports_eos_domain_error():
         assert e.value.code in (-4, -5)
 
 
+def test_autotune_keeps_a_raised_error():
+    # The state of the case above leaves the EOS domain; autotuning the handle afterwards
+    # must neither clear the sticky error nor touch the state or the launch shape.
+    L = lbm()
+    d = base(64, 32, T=0.485 * base(1, 1)["T"] / 0.8, tau=0.8)
+    with L.LbmAxi(gpu_params(d), droplet_rho(d, 10.0)) as sim:
+        sim.step(200)
+        with pytest.raises(L.LbmError) as e0:
+            sim.sync()
+        keep = sim.get_launch()
+        flags0 = sim.errors()
+        with pytest.raises(L.LbmError) as e:
+            sim.autotune(1)
+        assert e.value.code == e0.value.code
+        with pytest.raises(L.LbmError) as e:
+            sim.sync()
+        assert e.value.code == e0.value.code
+        assert np.array_equal(sim.errors(), flags0)
+        assert sim.get_launch() == keep
+
+
 @pytest.mark.parametrize("streams", [1, 2])
 def test_error_in_one_member_leaves_the_others_readable(streams):
     # A batch of a failing member (as above) and a sound one: the handle-wide sync reports

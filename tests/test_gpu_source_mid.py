@@ -1,0 +1,123 @@
+"""The link-midpoint source (Sec. 2.2, source_mid = 1) on the GPU against the oracle,
+through the C ABI: FP64 within 1e-10 (max norm, velocities against the velocity scale),
+every launch shape of the parity suite, the FP32 form bitwise across launch shapes, and
+batches that mix it with the node source (each member bitwise equal to its single run:
+the node-source member runs the deeper pipeline in the batch and the plain one alone)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from cases import base, droplet_rho, gpu_params, oracle_params, rel_inf
+from test_gpu_parity import LAUNCHES, assert_fp64_parity, run_pair, run_pair_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def lbm():
+    from paper_1512_01977_amd import lbm as L
+    return L
+
+
+def test_static_droplet_1000_steps_fp64():
+    # the 128 x 64 static droplet of the parity suite with the source at the link midpoint
+    d = base(128, 64, source_mid=1)
+    rho0 = droplet_rho(d, 20.0, noise=1e-4, seed=1)
+    print("case static droplet 128x64 fp64 1000 steps, link-midpoint source", flush=True)
+    assert_fp64_parity(*run_pair(d, rho0, 1000))
+
+
+VARIANTS = {
+    "free_slip": dict(),
+    "no_slip_top": dict(bc_top=1),
+    "guo": dict(forcing=1, A=-0.152, gz=2e-6),
+    "vdw": dict(eos=O.EOS_VDW, lam=0.01, T=0.8, tau=0.7),
+    "lattice_cs4": dict(faxis_sound=1, A=-0.152),
+    "two_d": dict(axisym=0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(VARIANTS))
+def test_variants_agree_with_oracle(name):
+    d = base(48, 30, source_mid=1, **VARIANTS[name])
+    rho0 = droplet_rho(d, 9.0, eps=0.15, zc=20.0)
+    print("case source_mid", name, flush=True)
+    assert_fp64_parity(*run_pair(d, rho0, 150))
+
+
+@pytest.mark.parametrize("launch", LAUNCHES,
+                         ids=lambda c: f"w{c['width']}s{c['seg_rows']}p{c['persistent']}"
+                                       f"x{c['xcd_swizzle']}r{c['regf']}")
+def test_launch_shapes_agree_with_oracle(launch):
+    d = base(150, 37, A=-0.152, tau=0.9, source_mid=1)
+    rho0 = droplet_rho(d, 11.0, eps=0.2, zc=70.0)
+    print("case source_mid", launch, flush=True)
+    assert_fp64_parity(*run_pair(d, rho0, 120, launch=launch))
+
+
+def test_narrow_and_short_domains():
+    # nz = 1 and 2 (every lane wraps onto one or two columns) and the fewest rows (nr = 4)
+    for nz, nr in ((1, 40), (2, 24), (20, 4)):
+        d = base(nz, nr, eos=O.EOS_IDEAL, tau=0.75, bc_top=1, source_mid=1)
+        rng = np.random.default_rng(nz)
+        rho0 = 1.0 + 0.02 * rng.standard_normal((nr, nz))
+        uz0 = 0.01 * rng.standard_normal((nr, nz))
+        print("case source_mid", nz, nr, flush=True)
+        assert_fp64_parity(*run_pair(d, rho0, 80, uz0=uz0))
+
+
+def test_fp32_form_launch_shapes_agree_bitwise():
+    d = base(150, 37, A=-0.152, tau=0.9, source_mid=1)
+    rho0 = droplet_rho(d, 11.0, eps=0.2, zc=70.0)
+    o, g0 = run_pair(d, rho0, 120, precision=1, launch=LAUNCHES[0])
+    ro, uzo, uro, _ = o
+    uscale = max(np.abs(uzo).max(), np.abs(uro).max())
+    er = rel_inf(g0[0], ro)
+    eu = max(np.abs(g0[1] - uzo).max(), np.abs(g0[2] - uro).max()) / uscale
+    print(f"FP32 vs oracle, link-midpoint source: rho {er:.2e}, u {eu:.2e}", flush=True)
+    assert er <= 1e-5 and eu <= 1e-4
+    for launch in LAUNCHES[1:]:
+        print("case", launch, flush=True)
+        g = run_pair_gpu(d, rho0, 120, 1, launch)
+        for a, b in zip(g, g0):
+            assert np.array_equal(a, b), launch
+
+
+def test_mixed_batch_equals_single_runs_bitwise():
+    L = lbm()
+    ds = [base(64, 32, A=-0.152, source_mid=1), base(48, 30, A=-0.152),
+          base(40, 24, forcing=1, A=-0.152, source_mid=1), base(40, 24, axisym=0, source_mid=1)]
+    rhos = [droplet_rho(d, 0.3 * d["nr"], eps=0.1, seed=40 + k) for k, d in enumerate(ds)]
+    for prec in (0, 1):
+        singles = []
+        for k, d in enumerate(ds):
+            with L.LbmAxi(gpu_params(d), rhos[k], precision=prec) as one:
+                one.step(50)
+                singles.append(one.get_f())
+        for launch in (None, dict(width=128, seg_rows=12, persistent=0, grid=0, xcd_swizzle=2, regf=1, streams=2),
+                       dict(width=64, seg_rows=9, persistent=1, grid=0, xcd_swizzle=0, regf=0, streams=1)):
+            with L.LbmAxi([gpu_params(d) for d in ds], rhos, precision=prec) as bat:
+                if launch:
+                    bat.set_launch(**launch)
+                    bat.set_graph_chunk(10)
+                for n in (21, 29):
+                    bat.step(n)
+                for k in range(len(ds)):
+                    assert np.array_equal(bat.get_f(k), singles[k]), (prec, launch, k)
+
+
+def test_differs_from_the_node_source():
+    # Same drop, both source placements: the states part (the variant is live), the
+    # axisymmetric mass of both stays within the same small budget.
+    L = lbm()
+    out = {}
+    for mid in (0, 1):
+        d = base(96, 48, A=-0.152, source_mid=mid)
+        rho0 = droplet_rho(d, 14.0, eps=0.2, seed=2)
+        with L.LbmAxi(gpu_params(d), rho0) as sim:
+            m0 = sim.mass()[0]
+            sim.step(500)
+            out[mid] = (sim.moments()[0], sim.mass()[0] / m0 - 1)
+    diff = np.abs(out[1][0] - out[0][0]).max()
+    print("state difference", diff, "mass drift node/mid", out[0][1], out[1][1], flush=True)
+    assert diff > 1e-8
+    assert abs(out[1][1]) < 1e-3 and abs(out[0][1]) < 1e-3

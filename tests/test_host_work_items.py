@@ -40,6 +40,8 @@ def check_list(driver, esize, width, seg, persistent, xcd, streams, members):
     groups, items = work_list(driver, esize, width, seg, persistent, xcd, streams, members)
     line = 128 // esize
     wout = (width - 12) // line * line
+    # seven halo lanes on either side (the link-midpoint source's pipeline) fit as well
+    assert wout + 14 <= width and wout == (width - 14) // line * line
     # stream groups: contiguous ranges covering the list, each instance in exactly one
     assert groups[0][1] == 0 and sum(g[2] for g in groups) == len(items)
     for a, b in zip(groups, groups[1:]):
@@ -60,7 +62,7 @@ def check_list(driver, esize, width, seg, persistent, xcd, streams, members):
     for inst, (nz, nr) in enumerate(members):
         mine = items[items[:, 0] == inst]
         pitch = -(-nz // line) * line
-        cap = (1 << 31) // (9 * pitch * esize) - 14
+        cap = (1 << 31) // (9 * pitch * esize) - 16
         seg_eff = min(seg if seg > 0 else nr, cap)
         assert np.all(mine[:, 1] % line == 0)
         assert np.all(mine[:, 2] == np.minimum(wout, nz - mine[:, 1]))
@@ -117,6 +119,6 @@ def test_benchmark_ensemble_work_list(driver):
 
 def test_segment_cap_for_wide_fp64_rows(driver):
     # 16384-wide FP64 rows: a row block is 1.18 MB, so a work item may span at most
-    # 2^31 / (9 * 16384 * 8) - 14 = 1806 rows; whole-column segments are split there.
+    # 2^31 / (9 * 16384 * 8) - 16 = 1804 rows; whole-column segments are split there.
     _, items = check_list(driver, 8, 256, 0, 0, 1, 1, [(16384, 4000)])
-    assert (items[:, 4] - items[:, 3]).max() == 1806
+    assert (items[:, 4] - items[:, 3]).max() == 1804
