@@ -208,6 +208,18 @@ lbm_status lbm_axi_moments(lbm_axi_t h, int32_t k, double* rho, double* uz, doub
 /* mass[k] = sum over nodes of 2 pi r_j rho, FP64, deterministic; mass is host [n]. */
 lbm_status lbm_axi_mass(lbm_axi_t h, double* mass);
 
+/* For callers that cannot allocate device memory or synchronise (code under stream capture,
+ * tight serving loops): lbm_axi_mass without allocation or host round trip.  Enqueues on the
+ * handle's stream the same fixed-order FP64 reduction, whose per-row partials live in the
+ * library's static device scratch (1 MiB per GPU, held until the process ends: at most
+ * 131072 rows over all instances of the handle, else LBM_ERR_UNSUPPORTED), and writes the n
+ * per-instance masses to mass_dev, a caller-owned device array of n doubles on the handle's
+ * device.  The result equals lbm_axi_mass's bitwise once the stream has reached it.  Allocates
+ * nothing and does not synchronise; device errors of the state are not reported here (call
+ * lbm_axi_sync).  Every call on one GPU shares that GPU's scratch: calls that overlap in time
+ * on one GPU (handles on different streams) race and must be ordered by the caller. */
+lbm_status lbm_axi_mass_async(lbm_axi_t h, double* mass_dev);
+
 /* dp[k] = mean P_k(rho) over nodes closer than r_in[k] to (zc[k], 0) minus the mean
  * over nodes farther than r_out[k] (Young-Laplace, eq. laplacepressure); host [n] arrays. */
 lbm_status lbm_axi_laplace(lbm_axi_t h, const double* zc, const double* r_in,

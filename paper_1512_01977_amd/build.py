@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm_axi.so")
-SOURCES = ["lbm_kernels.hip", "lbm_axi.cpp", "eos_host.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm_axi.cpp", "eos_host.cpp", "scratch.hip"]
 # No fast-math (the FP64 path is compared with an FP64 reference); multiply-adds are fused
 # only within one expression (-ffp-contract=on), so that every kernel instantiation rounds
 # the same arithmetic the same way; packed FP32 instructions are disabled.

@@ -10,6 +10,7 @@
 
 #include "lbm_axi.h"
 #include "lbm_axi_internal.h"
+#include "scratch.h"
 #include "work_items.h"
 
 using namespace lbm;
@@ -23,6 +24,7 @@ struct lbm_axi_s {
   long long felems = 0;  // elements of one distribution buffer (all instances, padded)
   long long nodes = 0;  // real nodes
   size_t esize = 8;
+  int device = 0;  // the device current at set-up, whose stream and memory the handle uses
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -461,6 +463,10 @@ lbm_status create(int n, const lbm_axi_params* params, int prec, const double* c
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
     return fail(LBM_ERR_HIP);
   h->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  h->device = dev;
+  // the static scratch of lbm_axi_mass_async on this device (looked up once per device; a
+  // failure only disables that entry point, which then reports it)
+  (void)scratch_attach();
   if (stream) {
     h->stream = static_cast<hipStream_t>(stream);
   } else {
@@ -731,6 +737,22 @@ static lbm_status reduce(lbm_axi_t h, int K, double* out) {
 lbm_status lbm_axi_mass(lbm_axi_t h, double* mass) {
   if (!h || !mass) return LBM_ERR_ARG;
   return reduce(h, 1, mass);
+}
+
+lbm_status lbm_axi_mass_async(lbm_axi_t h, double* mass_dev) {
+  if (!h || !mass_dev) return LBM_ERR_ARG;
+  // one FP64 partial per row of every instance in the device's static scratch
+  if ((size_t)h->n_rows * sizeof(double) > scratch_bytes()) return LBM_ERR_UNSUPPORTED;
+  double* part = static_cast<double*>(scratch_ptr(h->device));
+  if (!part) return LBM_ERR_HIP;
+  hipError_t e = h->prec == LBM_PREC_FP32
+                     ? launch_rows<float>(1, static_cast<const float*>(h->fbuf[h->cur]), h->d_inst, h->d_rows,
+                                          h->n_rows, nullptr, part, h->stream)
+                     : launch_rows<double>(1, static_cast<const double*>(h->fbuf[h->cur]), h->d_inst, h->d_rows,
+                                           h->n_rows, nullptr, part, h->stream);
+  if (e != hipSuccess) return LBM_ERR_HIP;
+  HIPCHK(launch_finish(1, part, h->d_row_start, h->d_inst, h->n, mass_dev, h->stream));
+  return LBM_OK;
 }
 
 lbm_status lbm_axi_laplace(lbm_axi_t h, const double* zc, const double* r_in, const double* r_out, double* dp) {

@@ -33,7 +33,7 @@ EXPORTS = [
     "lbm_axi_batch_init", "lbm_axi_workspace_bytes", "lbm_axi_batch_init_ws", "lbm_axi_destroy",
     "lbm_axi_step", "lbm_axi_step_timed", "lbm_axi_sync", "lbm_axi_errors",
     "lbm_axi_set_graph_chunk",
-    "lbm_axi_moments", "lbm_axi_mass", "lbm_axi_laplace", "lbm_axi_axis_interface",
+    "lbm_axi_moments", "lbm_axi_mass", "lbm_axi_mass_async", "lbm_axi_laplace", "lbm_axi_axis_interface",
     "lbm_axi_get_f", "lbm_axi_set_f",
     "lbm_axi_get_launch", "lbm_axi_set_launch", "lbm_axi_autotune", "lbm_axi_stream_copy",
     "lbm_axi_sizes",
@@ -139,6 +139,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_axi_set_graph_chunk.argtypes = [_H, ctypes.c_int32]
         L.lbm_axi_moments.argtypes = [_H, ctypes.c_int32, _dp, _dp, _dp]
         L.lbm_axi_mass.argtypes = [_H, _dp]
+        L.lbm_axi_mass_async.argtypes = [_H, ctypes.c_void_p]
         L.lbm_axi_laplace.argtypes = [_H, _dp, _dp, _dp, _dp]
         L.lbm_axi_axis_interface.argtypes = [_H, _dp, _dp, _dp]
         L.lbm_axi_get_f.argtypes = [_H, ctypes.c_int32, _dp]
@@ -295,6 +296,15 @@ class LbmAxi:
         m = np.empty(self.n)
         _check(lib().lbm_axi_mass(self.h, _ptr(m)), "lbm_axi_mass")
         return m
+
+    def mass_async(self, out) -> None:
+        """lbm_axi_mass_async: the masses into `out`, a float64 CUDA tensor of n elements on the
+        handle's device; enqueued on the handle's stream, nothing allocated, no synchronisation."""
+        import torch
+        if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64
+                and out.numel() >= self.n and out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 CUDA tensor of n elements")
+        _check(lib().lbm_axi_mass_async(self.h, ctypes.c_void_p(out.data_ptr())), "lbm_axi_mass_async")
 
     def laplace(self, zc, r_in, r_out) -> np.ndarray:
         zc, r_in, r_out = (np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.float64),
