@@ -5,7 +5,10 @@ A step is one time step of the whole method over every node of the workload:
 pull streaming, moments, FP64 EOS and pseudopotential, Kupershtokh force with the
 exact-difference shift, axisymmetric force correction and source terms, BGK.
 Default workload: the 256-member droplet ensemble in FP32 storage, all members in
-one launch per step, replayed as hipGraph chunks of 100 steps.  The same line
+one launch per step (per stream group), replayed as hipGraph chunks of up to 10
+steps (an even chunk that fits the requested step count, so short runs replay too;
+longer chunks start the second stream group later, by the host time of launching the
+first group's graph, which costs more than the fewer launches save).  The same line
 also reports the single large domain (16384 x 8192) in FP32 and in FP64.
 
 Prints one JSON line on stdout; progress goes to stderr.
@@ -73,6 +76,26 @@ def same_launch(a, b) -> bool:
                for k in keys)
 
 
+def settle_device(wl, launch, seconds=0.3):
+    """Bring the GPU out of its idle power state before a form's warm-up steps: from idle, a
+    step takes ~25 % longer for the first ~100 ms of load, and again after a second of idling
+    (the same state then ramps again; a memory-bound copy kernel only half warms it).  A
+    throwaway copy of the workload, in the same launch shape, is stepped for `seconds` and
+    discarded: the measured state still gets exactly its warm-up steps, and nothing of the
+    settling is timed."""
+    from paper_1512_01977_amd import lbm
+    tmp = lbm.LbmAxi(wl.params if len(wl.params) > 1 else wl.params[0],
+                     wl.rho0 if len(wl.params) > 1 else wl.rho0[0], precision=wl.precision)
+    try:
+        tmp.set_launch(**launch)
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            tmp.step(10)
+            tmp.sync()
+    finally:
+        tmp.close()
+
+
 def run_form(wl, steps, warmup, graph_chunk, shape, label):
     """shape: "profiled" runs the launch shape the committed byte counters were taken in
     (autotuning when there is none for the current kernel), "tune" autotunes unless the
@@ -87,7 +110,10 @@ def run_form(wl, steps, warmup, graph_chunk, shape, label):
                      wl.rho0 if len(wl.params) > 1 else wl.rho0[0], precision=wl.precision)
     log(f"[bench] {label}: state on the device in {time.perf_counter() - t0:.1f} s")
     rec = traffic_record(wl.name, dtype)
-    if shape == "profiled" and rec and rec.get("launch"):
+    if isinstance(shape, dict):
+        sim.set_launch(**shape)
+        launch, source = sim.get_launch(), "given"
+    elif shape == "profiled" and rec and rec.get("launch"):
         sim.set_launch(**rec["launch"])
         launch, source = sim.get_launch(), "profiled"
     else:
@@ -96,6 +122,7 @@ def run_form(wl, steps, warmup, graph_chunk, shape, label):
     log(f"[bench] {label}: launch {launch} ({source})")
     if graph_chunk:
         sim.set_graph_chunk(graph_chunk)
+    settle_device(wl, launch)
     sim.step(warmup)
     sim.sync()
     torch.cuda.synchronize()
@@ -111,17 +138,34 @@ def run_form(wl, steps, warmup, graph_chunk, shape, label):
     achieved = BYTES_PER_NODE[dtype] * nodes / per_launch_s / 1e9
     # the counted bytes belong to one launch shape: reported only when that shape ran
     traffic = rec.get("bytes_per_launch") if rec and same_launch(rec.get("launch"), launch) else None
+    # the bytes the profiler counted crossing the HBM interface in one step, over the same time
+    counted = traffic / per_launch_s / 1e9 if traffic else None
     res = {
         "workload": wl.name, "dtype": dtype, "nodes": nodes, "steps": steps,
+        "graph_chunk": graph_chunk,
         "ms_per_step": wall * 1e3 / steps, "kernel_ms_per_step": ev_ms / steps,
         "MLUPS": nodes * steps / wall / 1e6,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic},
+        "counted_hbm_GBps": counted,
+        "counted_hbm_frac": counted / HBM_PEAK_GBPS if counted else None,
         "launch": launch, "launch_source": source, "mass_after": mass,
     }
     log(f"[bench] {label}: {res['MLUPS']:.0f} MLUPS, {achieved:.0f} GB/s algorithmic "
-        f"({100 * achieved / HBM_PEAK_GBPS:.1f}% of HBM peak)")
+        f"({100 * achieved / HBM_PEAK_GBPS:.1f}% of HBM peak)"
+        + (f", {counted:.0f} GB/s counted ({100 * counted / HBM_PEAK_GBPS:.1f}%)" if counted else ""))
     return res
+
+
+def graph_chunk_for(steps: int, limit: int) -> int:
+    """The captured chunk for a run of `steps` steps: an even number of steps (a chunk must
+    end on the buffer it starts from) of at most `limit`, chosen to leave the fewest steps
+    to eager launches and, among those, the longest; 0 (eager only) below two steps."""
+    best = 0
+    for c in range(2, min(limit, steps) + 1, 2):
+        if best == 0 or (steps % c, -c) < (steps % best, -best):
+            best = c
+    return best
 
 
 def guo_workload():
@@ -191,11 +235,14 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp32", "fp64"])
     ap.add_argument("--forms", default="all", choices=["all", "main"],
                     help="all: also time the large single domain in FP32 and FP64")
-    ap.add_argument("--graph-chunk", type=int, default=100)
+    ap.add_argument("--graph-chunk", type=int, default=10,
+                    help="longest captured chunk of steps (an even chunk <= this that fits --steps is used)")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the launch shape (unless cached) instead of running the shape "
                          "the committed byte counters were taken in")
     ap.add_argument("--no-tune", action="store_true", help="use the cached or default launch shape")
+    ap.add_argument("--launch", default=None, metavar="JSON",
+                    help="launch shape of the main form as a JSON object of lbm_axi_launch fields")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stream-copy", type=int, default=0, metavar="BYTES",
                     help="only run the reference copy kernel on BYTES and print its GB/s")
@@ -224,9 +271,10 @@ def main():
     main_prec = prec[args.precision or default_prec[args.workload]]
     t_all = time.perf_counter()
     wl = workloads.REGISTRY[args.workload](precision=main_prec)
-    chunk = args.graph_chunk if args.steps >= args.graph_chunk else 0
+    chunk = graph_chunk_for(args.steps, args.graph_chunk)
     shape = "cached" if args.no_tune else "tune" if args.tune else "profiled"
-    main_res = run_form(wl, args.steps, args.warmup, chunk, shape, "main")
+    main_res = run_form(wl, args.steps, args.warmup, chunk,
+                        json.loads(args.launch) if args.launch else shape, "main")
 
     forms = [main_res]
     if args.forms == "all":
@@ -276,8 +324,10 @@ def main():
         "stream_copy_GBps": copy_gbps,
         "cpu_baseline": cpu,
         "cpu_baseline_1core": cpu1,
-        "forms": [{k: f[k] for k in ("workload", "dtype", "MLUPS", "ms_per_step",
-                                     "kernel_ms_per_step", "roofline", "launch", "launch_source")}
+        "counted_hbm_GBps": main_res["counted_hbm_GBps"],
+        "forms": [{k: f[k] for k in ("workload", "dtype", "MLUPS", "ms_per_step", "kernel_ms_per_step",
+                                     "graph_chunk", "roofline", "counted_hbm_GBps", "launch",
+                                     "launch_source")}
                   for f in forms],
         "wall_s": time.perf_counter() - t_all,
     }
