@@ -202,7 +202,9 @@ lbm_status lbm_axi_set_graph_chunk(lbm_axi_t h, int32_t chunk);
 /* rho and the physical velocity u = (j + F/2)/rho (Sec. 2.1) of instance k; host [nr][nz]
  * outputs (caller-owned).  LBM_ERR_ARG for a bad k or NULL output; LBM_ERR_EOS_DOMAIN or
  * LBM_ERR_NONFINITE if instance k has left the EOS domain (the outputs are then filled but
- * meaningless). */
+ * meaningless).  The first call allocates a device buffer for three fields of the largest
+ * instance and the per-instance work lists, kept until lbm_axi_destroy (rebuilt after a
+ * change of strip width or segment length). */
 lbm_status lbm_axi_moments(lbm_axi_t h, int32_t k, double* rho, double* uz, double* ur);
 
 /* mass[k] = sum over nodes of 2 pi r_j rho, FP64, deterministic; mass is host [n]. */

@@ -61,6 +61,12 @@ struct lbm_axi_s {
   Group grp[kMaxStreams];
   int n_groups = 1;
   hipEvent_t fork = nullptr;
+  // Moments: one instance's three fields and every instance's work list of the moments
+  // launch (at the current strip width and segment length), set up on first use.
+  double* d_mom = nullptr;
+  WorkItem* d_mitems = nullptr;
+  std::vector<int> mfirst, mcount;
+  int m_width = 0, m_seg = -1;
 };
 
 namespace {
@@ -355,7 +361,7 @@ void free_all(lbm_axi_s* h) {
     if (h->fbuf[0]) (void)hipFree(h->fbuf[0]);
   }
   void* ptrs[] = {h->d_inst, h->d_items, h->d_queue, h->d_err, h->d_rows, h->d_row_start,
-                  h->d_part, h->d_out, h->d_geo};
+                  h->d_part, h->d_out, h->d_geo, h->d_mom, h->d_mitems};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -515,23 +521,54 @@ lbm_status create(int n, const lbm_axi_params* params, int prec, const double* c
   return LBM_OK;
 }
 
+// The moments launch of instance k (its own work list, one workgroup per item).
 template <typename R>
 hipError_t enqueue_moments(lbm_axi_s* h, int k, double* mr, double* mz, double* mu) {
-  // A dedicated work list for instance k, non-persistent, same width.
   SweepArgs<R> g{};
   g.fin = static_cast<const R*>(h->fbuf[h->cur]);
   g.fout = static_cast<R*>(h->fbuf[h->cur ^ 1]);
   g.inst = h->d_inst;
-  g.items = h->d_items;
-  g.n_items = h->n_items;
+  g.items = h->d_mitems + h->mfirst[k];
+  g.n_items = h->mcount[k];
   g.xcd_swizzle = 0;
   g.queue = h->d_queue;
   g.err = h->d_err;
   g.mrho = mr;
   g.muz = mz;
   g.mur = mu;
-  (void)k;
-  return sweep_dispatch<R>(g, h->launch.width, true, false, false, false, false, h->n_items, h->stream);
+  return sweep_dispatch<R>(g, h->launch.width, true, false, false, false, false, g.n_items, h->stream);
+}
+
+// Work lists of the moments launches and the field buffer, (re)built when first needed and
+// when the strip width or segment length has changed since.
+lbm_status prepare_moments(lbm_axi_s* h) {
+  if (!h->d_mom) {
+    size_t most = 0;
+    for (const auto& p : h->prm) most = std::max(most, (size_t)p.nz * p.nr);
+    HIPCHK(hipMalloc(&h->d_mom, 3 * most * sizeof(double)));
+  }
+  if (h->m_width == h->launch.width && h->m_seg == h->launch.seg_rows) return LBM_OK;
+  std::vector<WorkItem> all;
+  h->mfirst.assign(h->n, 0);
+  h->mcount.assign(h->n, 0);
+  for (int k = 0; k < h->n; ++k) {
+    std::vector<char> only(h->n, 0);
+    only[k] = 1;
+    const std::vector<WorkItem> items = build_items(
+        h->prm, (int)h->esize, lbm_axi_launch{h->launch.width, h->launch.seg_rows, 0, 0, 0, 0, 1}, only);
+    h->mfirst[k] = (int)all.size();
+    h->mcount[k] = (int)items.size();
+    all.insert(all.end(), items.begin(), items.end());
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (h->d_mitems) HIPCHK(hipFree(h->d_mitems));
+  h->d_mitems = nullptr;
+  h->m_width = 0;
+  HIPCHK(hipMalloc(&h->d_mitems, all.size() * sizeof(WorkItem)));
+  HIPCHK(hipMemcpy(h->d_mitems, all.data(), all.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+  h->m_width = h->launch.width;
+  h->m_seg = h->launch.seg_rows;
+  return LBM_OK;
 }
 
 }  // namespace
@@ -683,41 +720,17 @@ lbm_status lbm_axi_moments(lbm_axi_t h, int32_t k, double* rho, double* uz, doub
   if (!h || k < 0 || k >= h->n || !rho || !uz || !ur) return LBM_ERR_ARG;
   const auto& p = h->prm[k];
   const size_t n = (size_t)p.nz * p.nr;
-  double* tmp = nullptr;
-  HIPCHK(hipMalloc(&tmp, 3 * n * sizeof(double)));
-  // moments of instance k: a work list restricted to it
-  const int saved_items = h->n_items;
-  std::vector<char> only(h->n, 0);
-  only[k] = 1;
-  std::vector<WorkItem> items =
-      build_items(h->prm, (int)h->esize, lbm_axi_launch{h->launch.width, h->launch.seg_rows, 0, 0, 0, 0, 1}, only);
-  WorkItem* d_items = nullptr;
-  lbm_status st = LBM_OK;
-  if (hipMalloc(&d_items, items.size() * sizeof(WorkItem)) != hipSuccess) st = LBM_ERR_ALLOC;
-  if (st == LBM_OK &&
-      hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, h->stream) !=
-          hipSuccess)
-    st = LBM_ERR_HIP;
-  if (st == LBM_OK) {
-    WorkItem* keep = h->d_items;
-    h->d_items = d_items;
-    h->n_items = (int)items.size();
-    hipError_t e = h->prec == LBM_PREC_FP32 ? enqueue_moments<float>(h, k, tmp, tmp + n, tmp + 2 * n)
-                                            : enqueue_moments<double>(h, k, tmp, tmp + n, tmp + 2 * n);
-    h->d_items = keep;
-    h->n_items = saved_items;
-    if (e != hipSuccess) st = LBM_ERR_HIP;
-  }
-  if (st == LBM_OK) {
-    if (hipMemcpyAsync(rho, tmp, n * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
-        hipMemcpyAsync(uz, tmp + n, n * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
-        hipMemcpyAsync(ur, tmp + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
-        hipStreamSynchronize(h->stream) != hipSuccess)
-      st = LBM_ERR_HIP;
-  }
-  (void)hipFree(d_items);
-  (void)hipFree(tmp);
+  lbm_status st = prepare_moments(h);
   if (st != LBM_OK) return st;
+  double* tmp = h->d_mom;
+  hipError_t e = h->prec == LBM_PREC_FP32 ? enqueue_moments<float>(h, k, tmp, tmp + n, tmp + 2 * n)
+                                          : enqueue_moments<double>(h, k, tmp, tmp + n, tmp + 2 * n);
+  if (e != hipSuccess ||
+      hipMemcpyAsync(rho, tmp, n * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipMemcpyAsync(uz, tmp + n, n * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipMemcpyAsync(ur, tmp + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return LBM_ERR_HIP;
   return read_err(h, k);
 }
 

@@ -45,6 +45,23 @@ def droplet(nz: int, nr: int, rho_v: float, rho_l: float, radius: float,
     return np.ascontiguousarray(rho * (1.0 + _noise(rho.shape, noise, seed)))
 
 
+def ellipsoid(nz: int, nr: int, rho_v: float, rho_l: float, r_a: float, r_z: float,
+              zc: float | None = None, width: float = 5.0, noise: float = 0.0,
+              seed: int = 0) -> np.ndarray:
+    """Axisymmetric ellipsoidal drop (r/r_a)^2 + ((z - zc)/r_z)^2 = 1 on the axis (Sec. 3.2):
+    the droplet profile with R(theta) the ellipse's distance from its centre along the ray,
+    1 / R(theta)^2 = (sin theta / r_a)^2 + (cos theta / r_z)^2; then rho <- rho (1 + xi)."""
+    if zc is None:
+        zc = nz / 2.0
+    z = np.arange(nz, dtype=np.float64) - zc
+    r = np.arange(nr, dtype=np.float64) + 0.5
+    Z, Rr = np.meshgrid(z, r)
+    d = np.sqrt(Z * Z + Rr * Rr)
+    rad = 1.0 / np.sqrt((Rr / (d * r_a)) ** 2 + (Z / (d * r_z)) ** 2)
+    rho = 0.5 * (rho_l + rho_v) - 0.5 * (rho_l - rho_v) * np.tanh(2.0 * (d - rad) / width)
+    return np.ascontiguousarray(rho * (1.0 + _noise(rho.shape, noise, seed)))
+
+
 def radial_wave(nz: int, nr: int, rho_g: float, amplitude: float = 1e-2,
                 wavelength: float = 256.0, noise: float = 0.0, seed: int = 0) -> np.ndarray:
     """Single-phase field rho_g (1 + amplitude cos(2 pi r / wavelength)) (1 + xi)."""

@@ -104,6 +104,42 @@ def test_large_domain_full_size_bench_launch(precision, large_oracle):
         assert er <= 5e-6 and eu <= 5e-5
 
 
+SINGLE_STEPS = {"mode2": 20, "wave": 4}
+
+
+@pytest.fixture(scope="module")
+def single_oracle():
+    from paper_1512_01977_amd import workloads
+    out = {}
+    for name, steps in SINGLE_STEPS.items():
+        wl = workloads.REGISTRY[name](precision=0)
+        out[name] = oracle_moments(wl.params[0], wl.rho0[0], steps)
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("name", sorted(SINGLE_STEPS))
+def test_single_domain_workloads_full_size(name, precision, single_oracle):
+    # The mode-2 droplet at density ratio ~1e3 (1024 x 512, 524 288 nodes) after 20 steps and
+    # the density wave (4096 x 2048 with a no-slip wall, 8 388 608 nodes) after 4 steps, every
+    # node against the oracle, in the tuner's launch shape for the workload.
+    # The FP32 velocity is bounded in lattice units: the momentum is a sum of FP32 populations
+    # of size ~w_i rho, so u carries an absolute rounding error of order the FP32 unit
+    # roundoff whatever its own size (the wave starts at rest: after 4 steps its velocity scale
+    # is small enough for that to be 2e-4 of it).
+    from paper_1512_01977_amd import workloads
+    wl = workloads.REGISTRY[name](precision=precision)
+    (g,) = run_gpu(wl, SINGLE_STEPS[name], 0)
+    er, eu = field_errors(g, single_oracle[name])
+    ua = max(float(np.abs(g[1] - single_oracle[name][1]).max()), float(np.abs(g[2] - single_oracle[name][2]).max()))
+    print(f"{wl.name} precision {precision}: rho err {er:.3e}, u err {eu:.3e} of its scale, "
+          f"{ua:.3e} absolute", flush=True)
+    if precision == 0:
+        assert max(er, eu) <= 1e-10
+    else:
+        assert er <= 5e-6 and ua <= 1e-6
+
+
 def test_fp64_domain_beyond_four_gib_per_three_planes():
     # 16384 x 12288 in FP64 (201M nodes, 14.5 GB per distribution buffer): three direction
     # planes span 4.8 GB, more than 32-bit offsets reach from one base; the step kernel
