@@ -46,7 +46,12 @@ struct WorkItem {
 // The nine planes of a row sit next to each other (a row block), so that the rows a
 // workgroup reads and writes in one step are close together in memory.
 inline int line_elems(int esize) { return 128 / esize; }
-inline int row_pitch(int nz, int esize) { return (nz + line_elems(esize) - 1) / line_elems(esize) * line_elems(esize); }
+// A pitch that is a multiple of 2 KiB gets one more line, so that the nine planes of a row
+// block do not sit at a power-of-two stride (measured 1-1.5 % faster on 16384-wide rows).
+inline int row_pitch(int nz, int esize) {
+  const int p = (nz + line_elems(esize) - 1) / line_elems(esize) * line_elems(esize);
+  return (p * esize) % 2048 == 0 ? p + line_elems(esize) : p;
+}
 inline int strip_cols(int width, int esize) {
   // output columns of a workgroup of `width` lanes: six halo lanes on either side (seven
   // with the link-midpoint source; for every width and element size the whole lines that

@@ -121,3 +121,33 @@ def test_differs_from_the_node_source():
     print("state difference", diff, "mass drift node/mid", out[0][1], out[1][1], flush=True)
     assert diff > 1e-8
     assert abs(out[1][1]) < 1e-3 and abs(out[0][1]) < 1e-3
+
+
+def test_surface_tension_and_mode2_frequency_against_the_node_source():
+    # The Sec. 3.1-3.2 observables with the source at the link midpoint: the static drop's
+    # sigma (vdW T = 0.8, A = 0, lambda = 0.01, R = 80, tau = 1) next to the node source's, and
+    # the mode-2 frequency of the R0 = 80 ellipsoid (tau = 0.7) against eq. (oscillatingfreq)
+    # at the variant's own sigma.  The source moves only O(k) along each link, so both stay
+    # within the node source's tolerances.
+    import dataclasses
+    L = lbm()
+    from paper_1512_01977_amd import inputs
+    from test_gpu_validation import fit_paper, lamb_omega, oscillate, r_eq, static_sigma
+    base_p = L.Params(nz=500, nr=250, tau=1.0, eos=L.EOS_VDW, T=0.8, lam=0.01, A=0.0)
+    out = {}
+    for mid in (0, 1):
+        p = dataclasses.replace(base_p, source_mid=mid)
+        sig, rl, rv = static_sigma(p, 80.0, 250.0)
+        q = dataclasses.replace(p, tau=0.7)
+        ra = 80.0 / 1.3 ** (1 / 3)
+        rho0 = inputs.ellipsoid(500, 250, rv, rl, ra, 1.3 * ra, zc=250.0, width=10.0)
+        t, y, rho_end = oscillate(q, rho0, 250.0, 0.5 * (rv + rl), 60000, 100, L.PREC_FP64)
+        R, rin, rout = r_eq(rho_end, 250.0, 80.0, 1)
+        m = t >= 2000
+        w = fit_paper(t[m], y[m])[3]
+        out[mid] = (sig, w, w / lamb_omega(sig, R, rin, rout, (0.7 - 0.5) / 3) - 1)
+    print(f"node source: sigma_lv {out[0][0] / 0.01:.4f}, omega {out[0][1]:.4e} ({out[0][2]:+.3f} vs Lamb); "
+          f"link midpoint: sigma_lv {out[1][0] / 0.01:.4f}, omega {out[1][1]:.4e} ({out[1][2]:+.3f})",
+          flush=True)
+    assert out[1][0] == pytest.approx(out[0][0], rel=0.05)
+    assert abs(out[1][2]) <= 0.06
