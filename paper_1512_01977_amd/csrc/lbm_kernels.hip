@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "lbm_axi_internal.h"
 
@@ -366,6 +367,17 @@ __device__ __forceinline__ float psi_shifted(double psi2, double psi_ref, double
   return num * recip(__builtin_fmaxf(den, 1e-30f));
 }
 
+// Calls f(integral_constant<P>, t0 + P) for P = 0 .. N - 1 while t0 + P < tend.
+template <int P, int N, typename F>
+__device__ __forceinline__ void unrolled_rows(F& f, int t0, int tend) {
+  if constexpr (P < N) {
+    if (t0 + P < tend) {
+      f(std::integral_constant<int, P>{}, t0 + P);
+      unrolled_rows<P + 1, N>(f, t0, tend);
+    }
+  }
+}
+
 // REGF: carry the populations gathered in stage A in registers until the collision instead
 // of gathering them again there (fewer loads that miss L2, more registers).
 // MID: some instance takes the source h_i at the link midpoint x + c_i/2 (Sec. 2.2) as the
@@ -426,9 +438,24 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
 
   // node values travelling from stage A to stage C (age 4) and to the collision (age LAG),
   // and from B/C onward
-  R sg_d[LAG + 1], jz_d[LAG + 1], jr_d[LAG + 1], kap_d[5];
+  // The row gathered at iteration t sits in slot (t - a_lo) mod PER of fd (and, when the
+  // populations are gathered again for the collision, of sg_s, jz_s, jr_s) until its
+  // collision LAG iterations later.  The row loop is unrolled PER times so that every slot
+  // index is a constant: the carried rows need no register moves, and the next row is
+  // gathered straight into its slot (PER = LAG + 2, so that slot is not the one the
+  // collision reads).  With the populations in registers (REGF) the moments of a row are
+  // summed again from them where they are needed (the same sums in the same order, so the
+  // same values) instead of being carried: that keeps the budget at three waves per SIMD.
+  constexpr int PER = LAG + 2;
+  constexpr int MS = REGF ? 1 : PER;
+  R sg_s[MS], jz_s[MS], jr_s[MS], kap_d[5];
 #pragma unroll
-  for (int q = 0; q <= LAG; ++q) sg_d[q] = jz_d[q] = jr_d[q] = R(0);
+  for (int q = 0; q < MS; ++q) sg_s[q] = jz_s[q] = jr_s[q] = R(0);
+  auto moments = [](const R* f, R& sg, R& jz, R& jr) {
+    sg = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    jz = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+    jr = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+  };
 #pragma unroll
   for (int q = 0; q < 5; ++q) kap_d[q] = R(0);
   R fk0z = 0, fk0r = 0, fk1z = 0, fk1r = 0, fk2z = 0, fk2r = 0;
@@ -438,14 +465,24 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
   R ir0 = 0, ir1 = 0, ir2 = 0;  // 1/r of the stage-C row, two iterations deep
   int bad = 0;
 
-  R fd[REGF ? LAG + 1 : 1][9];  // populations of rows t .. t - LAG (REGF only)
+  R fd[REGF ? PER : 1][9];  // populations of the rows in flight (REGF only), by slot
 #pragma unroll
-  for (int a = 0; a < (REGF ? LAG + 1 : 1); ++a)
+  for (int a = 0; a < (REGF ? PER : 1); ++a)
 #pragma unroll
     for (int i = 0; i < 9; ++i) fd[a][i] = R(0);
 
   R fa[9], fg[9];
-  if (a_lo < a_hi) gather_row<R>(pin, nr, I.bc_top, a_lo, x0, bm, bcol, bp, fa);
+  // moments of the row in slot sl
+  auto carried = [&](int sl, R& sg, R& jz, R& jr) {
+    if (REGF) {
+      moments(fd[REGF ? sl : 0], sg, jz, jr);
+    } else {
+      sg = sg_s[REGF ? 0 : sl];
+      jz = jz_s[REGF ? 0 : sl];
+      jr = jr_s[REGF ? 0 : sl];
+    }
+  };
+  if (a_lo < a_hi) gather_row<R>(pin, nr, I.bc_top, a_lo, x0, bm, bcol, bp, REGF ? fd[0] : fa);
   if (!REGF && !MOMENTS && s < e) gather_row<R>(pin, nr, I.bc_top, s, x0, bm, bcol, bp, fg);
   if (!MOMENTS) {  // the (dropped) stores of a step, so that loop entry looks like a loop iteration
 #pragma unroll
@@ -454,11 +491,11 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
 
   // Populations of row x for its collision: carried in registers (REGF) or the row gathered
   // one collision ahead, whose successor is gathered now.
-  auto take_f = [&](int x, R f[9]) {
+  auto take_f = [&](int x, int sl, R f[9]) {
     if (x < s || x >= e) return;
     if (REGF) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) f[i] = fd[REGF ? LAG : 0][i];
+      for (int i = 0; i < 9; ++i) f[i] = fd[REGF ? sl : 0][i];
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[i] = fg[i];
@@ -467,13 +504,14 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
   };
   // Collision of row x (eq. lbm) and the nine stores of its populations; h_i enters through
   // m0 and 3H (node source), or per direction through hmid (link-midpoint source, MID).
-  auto collide_store = [&](int x, const R f[9], R m0, R H3z, R H3r, const R* hmid) {
+  auto collide_store = [&](int x, int sl, const R f[9], R m0, R H3z, R H3r, const R* hmid) {
     const bool active = x >= s && x < e;
     R o[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) o[i] = __builtin_nondeterministic_value(R(0));
     if (active) {
-      const R sg = sg_d[LAG], jz = jz_d[LAG], jr = jr_d[LAG];
+      R sg, jz, jr;
+      carried(sl, sg, jz, jr);
       const R rho = rho_ref + sg;
       collide<R>(f, rho, sg, jz, jr, fcz[LAG - 4], fcr[LAG - 4], m0, H3z, H3r, omega, guo, o);
       if (MID && hmid) {
@@ -489,19 +527,10 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
     for (int i = 0; i < 9; ++i) bstore(o[i], pout.g, voff, orow + i * pout.pstride);
   };
 
-  for (int t = a_lo; t < e + LAG; ++t) {
-    if (REGF) {
-#pragma unroll
-      for (int a = LAG; a > 0; --a)
-#pragma unroll
-        for (int i = 0; i < 9; ++i) fd[REGF ? a : 0][i] = fd[REGF ? a - 1 : 0][i];
-    }
-#pragma unroll
-    for (int q = LAG; q > 0; --q) {
-      sg_d[q] = sg_d[q - 1];
-      jz_d[q] = jz_d[q - 1];
-      jr_d[q] = jr_d[q - 1];
-    }
+  auto row = [&](auto Pc, int t) {
+    constexpr int P = decltype(Pc)::value;
+    constexpr int S0 = P, S1 = (P + 1) % PER;                  // this row's slot, the next row's
+    constexpr int S4 = (P + PER - 4) % PER, S6 = (P + PER - 6) % PER, SL = (P + PER - LAG) % PER;
 #pragma unroll
     for (int q = 4; q > 0; --q) kap_d[q] = kap_d[q - 1];
     fk2z = fk1z; fk2r = fk1r; fk1z = fk0z; fk1r = fk0r;
@@ -515,15 +544,10 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
     {
       const int x = t;
       if (x >= a_lo && x < a_hi) {
-        const R* f = fa;
-        const R sg = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-        const R jz = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-        const R jr = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-        if (REGF) {
-#pragma unroll
-          for (int i = 0; i < 9; ++i) fd[0][i] = f[i];
-        }
-        if (x + 1 < a_hi) gather_row<R>(pin, nr, I.bc_top, x + 1, x0, bm, bcol, bp, fa);
+        const R* f = REGF ? fd[REGF ? S0 : 0] : fa;
+        R sg, jz, jr;
+        moments(f, sg, jz, jr);
+        if (x + 1 < a_hi) gather_row<R>(pin, nr, I.bc_top, x + 1, x0, bm, bcol, bp, REGF ? fd[REGF ? S1 : 0] : fa);
         const double rd = I.rho_ref + (double)sg;  // rho in FP64 for the EOS
         double Pk, kap;
         eos_dev(I, rd, Pk, kap);
@@ -534,9 +558,11 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         L.at(R_PSI, rb[0], 0) = psi;
         if (x == 0) L.at(R_PSI, rb[1], 0) = psi;  // psi is even across the axis: row -1 = row t - 1
         if (x == 1) L.at(R_PSI, rb[3], 0) = psi;  // row -2 = row t - 3
-        sg_d[0] = sg;
-        jz_d[0] = jz;
-        jr_d[0] = jr;
+        if (!REGF) {
+          sg_s[REGF ? 0 : S0] = sg;
+          jz_s[REGF ? 0 : S0] = jz;
+          jr_s[REGF ? 0 : S0] = jr;
+        }
         kap_d[0] = R(kap);
       } else if (a_hi == nr && x == nr) {
         L.at(R_PSI, rb[0], 0) = L.at(R_PSI, rb[1], 0);  // even at the wall: row nr = row nr - 1
@@ -587,7 +613,9 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
       const int x = t - 4;
       if (x >= c_lo && x < c_hi) {
         const Rows5 r{rb[1], rb[0], rb[4], rb[3], rb[2]};
-        const R rho = rho_ref + sg_d[4], jz = jz_d[4], jr = jr_d[4], kap = kap_d[4];
+        R sg4, jz, jr;
+        carried(S4, sg4, jz, jr);
+        const R rho = rho_ref + sg4, kap = kap_d[4];
         R fz = fk2z, fr = fk2r;
         if (I.axisym) {
           // F_axis = 3K/r [psi D_rz psi + 6A D_r psi D_z psi, psi (D_rr psi - D_r psi / r) + 6A (D_r psi)^2]
@@ -635,10 +663,12 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
       R m0 = R(0), H3z = R(0), H3r = R(0);
       const bool hrow = MID ? (x >= d_lo && x < d_hi) : (x >= s && x < e);
       R f[9];
-      if (!MID) take_f(x, f);
+      if (!MID) take_f(x, SL, f);
       if (I.axisym && hrow) {
         const Rows5 r{rb[3], rb[2], rb[1], rb[0], rb[4]};
-        const R rho = rho_ref + sg_d[6];
+        R sg6, jz6, jr6;
+        carried(S6, sg6, jz6, jr6);
+        const R rho = rho_ref + sg6;
         const R uz = L.at(R_UZ, r.s0, 0), ur = L.at(R_UR, r.s0, 0);
         const R druz = stencil_dr36<R, W>(L, R_UZ, r);  // 36 D_r u_z
         const R dzur = stencil_dz36<R, W>(L, R_UR, r);  // 36 D_z u_r
@@ -652,7 +682,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         m0 = -rur * ir;
       }
       if (!MID) {
-        collide_store(x, f, m0, H3z, H3r, nullptr);
+        collide_store(x, SL, f, m0, H3z, H3r, nullptr);
       } else {
         // the source ring: element (row slot, column, field), fields m0, 3H_z, 3H_r; the
         // row below the axis and the row beyond the wall hold the mirror values
@@ -672,9 +702,9 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         lds_barrier();
         // ---------------------------------------------------------------- E: row t-7 (rows t-8 .. t-6)
         const int xe = t - 7;
-        take_f(xe, f);
+        take_f(xe, SL, f);
         if (!mid) {
-          collide_store(xe, f, H(xe, 0, 0), H(xe, 0, 1), H(xe, 0, 2), nullptr);
+          collide_store(xe, SL, f, H(xe, 0, 0), H(xe, 0, 1), H(xe, 0, 2), nullptr);
         } else {
           // h_i(x + c_i/2) = (h_i(x) + h_i(x + c_i)) / 2, h_i = w_i (m0 + c_iz 3H_z + c_ir 3H_r)
           const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 18.0), w2 = R(1.0 / 72.0);  // w_i / 2 for i > 0
@@ -693,7 +723,7 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
           hm[6] = link(1, -1, w2, -1, 1);
           hm[7] = link(-1, -1, w2, -1, -1);
           hm[8] = link(-1, 1, w2, 1, -1);
-          collide_store(xe, f, R(0), R(0), R(0), hm);
+          collide_store(xe, SL, f, R(0), R(0), R(0), hm);
         }
       }
     }
@@ -705,7 +735,8 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
       rb[1] = rb[0];
       rb[0] = r4;
     }
-  }
+  };
+  for (int t0 = a_lo; t0 < e + LAG; t0 += PER) unrolled_rows<0, PER>(row, t0, e + LAG);
   if (bad) {
     atomicOr(g.err, bad);                 // any instance
     atomicOr(g.err + 1 + wi.inst, bad);   // this instance
@@ -719,7 +750,7 @@ __device__ __forceinline__ int xcd_map(int b, int G) {
   return xcd < rem ? xcd * (q + 1) + pos : rem * (q + 1) + (xcd - rem) * q + pos;
 }
 
-// Minimum waves per SIMD asked of the register allocator (128 VGPRs for four waves in FP32,
+// Minimum waves per SIMD asked of the register allocator (170 VGPRs for three waves in FP32,
 // 256 for two in FP64).  The budget must not force spills: a spill reload goes through the
 // vector memory counter and would make the wave wait for its prefetched rows.  The
 // persistent loop keeps more state live and the variants that carry the populations in
@@ -728,7 +759,7 @@ __device__ __forceinline__ int xcd_map(int b, int G) {
 // FP64 when gathering again, two and one with the populations in registers.
 template <typename R, bool PERSIST, bool REGF, bool MID>
 struct SweepWaves {
-  static constexpr int base = REGF ? (sizeof(R) == 4 ? 3 : 1) : (sizeof(R) == 4 ? 4 : 2);
+  static constexpr int base = REGF ? (sizeof(R) == 4 ? 3 : 1) : (sizeof(R) == 4 ? 3 : 2);
   static constexpr int mid = REGF ? (sizeof(R) == 4 ? 2 : 1) : (sizeof(R) == 4 ? 3 : 2);
   static constexpr int value = MID ? mid : (PERSIST && !REGF) ? base - 1 : base;
 };
