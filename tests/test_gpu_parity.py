@@ -86,6 +86,19 @@ def test_launch_shapes_agree_with_oracle(launch):
     assert_fp64_parity(*run_pair(d, rho0, 120, launch=launch))
 
 
+@pytest.mark.parametrize("width", [128, 256])
+def test_several_strips_per_row_agree_with_oracle(width):
+    # nz = 800 spans several strips (256 lanes: 224 x 3 + 128 columns, the last strip's upper
+    # wave ends at once), segments of 12 rows, one workgroup per item
+    # with the populations in registers and the persistent queue gathering them again
+    d = base(800, 30, A=-0.152, tau=0.85)
+    rho0 = droplet_rho(d, 10.0, eps=0.2, zc=400.0, seed=7)
+    for regf, pers in ((1, 0), (0, 1)):
+        launch = dict(width=width, seg_rows=12, persistent=pers, xcd_swizzle=2 if not pers else 0, regf=regf)
+        print("case nz 800", launch, flush=True)
+        assert_fp64_parity(*run_pair(d, rho0, 60, launch=launch))
+
+
 def test_fp32_form_launch_shapes_agree_bitwise():
     # The FP32 form in every launch shape of the list above on the same case: the
     # decomposition into strips (whole 128-byte lines: 32 floats) and segments does not
