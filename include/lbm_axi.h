@@ -191,10 +191,10 @@ lbm_status lbm_axi_sync(lbm_axi_t h);
 lbm_status lbm_axi_errors(lbm_axi_t h, int32_t* flags);
 
 /* Replay steps as captured hipGraphs of `chunk` steps (even, >= 2); 0 = eager launches.
- * The chunk starting from the current buffer is captured by this call (nothing runs); the
- * one starting from the other buffer, when a step first needs it.  A later set_launch
- * drops the captured chunks (captured again when next needed).  LBM_ERR_ARG for an odd or
- * negative chunk, LBM_ERR_HIP if the capture fails. */
+ * The chunks starting from either buffer are captured and uploaded by this call (no step
+ * runs; the call waits for the uploads), so that no step call spends host time capturing.
+ * A later set_launch drops them (captured again when a step next needs one).  LBM_ERR_ARG
+ * for an odd or negative chunk, LBM_ERR_HIP if the capture fails. */
 lbm_status lbm_axi_set_graph_chunk(lbm_axi_t h, int32_t chunk);
 
 /* ---------------------------------------------------------------- observables (synchronising) */

@@ -287,12 +287,15 @@ lbm_status capture_group(lbm_axi_s* h, int grp, int cur) {
     L.gexec[cur] = nullptr;
     return LBM_ERR_HIP;
   }
+  // the executable's one-time device set-up now, not in its first launch
+  HIPCHK(hipGraphUpload(L.gexec[cur], L.st));
   return LBM_OK;
 }
 
 // nsteps steps of every instance, ordered after earlier work on the handle's stream and
 // before later work on it.  Whole graph chunks are replayed (a chunk is even, so it ends on
-// the buffer it started from; the chunk of each starting buffer is captured when first
+// the buffer it started from; lbm_axi_set_graph_chunk captures the chunks of both starting
+// buffers, and one dropped by a change of launch shape is captured again here when
 // needed), the rest launched one by one; both go out one step or chunk per group in turn,
 // so that every group's stream has work from the start.
 lbm_status run_steps(lbm_axi_s* h, int64_t nsteps, bool graphs) {
@@ -707,12 +710,14 @@ lbm_status lbm_axi_set_graph_chunk(lbm_axi_t h, int32_t chunk) {
   if (!h || chunk < 0 || (chunk > 0 && (chunk < 2 || (chunk & 1)))) return LBM_ERR_ARG;
   drop_graph(h);
   h->graph_chunk = chunk;
-  // capture now, from the buffer the next step starts from, so that the first steps do not
-  // wait for it (the chunk from the other buffer is captured when first needed)
-  for (int g = 0; g < h->n_groups && chunk > 0; ++g) {
-    lbm_status s = capture_group(h, g, h->cur);
-    if (s != LBM_OK) return s;
-  }
+  // capture now the chunks from both buffers, so that no later step call (one that starts
+  // on the other buffer after an odd number of eager steps, say) waits for a capture
+  for (int b = 0; b < 2 && chunk > 0; ++b)
+    for (int g = 0; g < h->n_groups; ++g) {
+      lbm_status s = capture_group(h, g, h->cur ^ b);
+      if (s != LBM_OK) return s;
+    }
+  for (int g = 0; g < h->n_groups && chunk > 0; ++g) HIPCHK(hipStreamSynchronize(h->grp[g].st));
   return LBM_OK;
 }
 

@@ -386,7 +386,8 @@ __device__ __forceinline__ void unrolled_rows(F& f, int t0, int tend) {
 // per-direction means (ghost rows across the axis and the wall hold the mirror values:
 // m0 and H_z even, H_r odd).  That adds a row to the pipeline and a column to the halo.
 template <typename R, int W, bool MOMENTS, bool REGF, bool GUO, bool MID>
-__device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem wi, char* lds, R* hring, int lane) {
+__device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem wi, char* lds, R* hring, R* mring,
+                                         int lane) {
   constexpr int HALO = MID ? 7 : 6;  // columns of halo on either side of the output strip
   constexpr int LAG = MID ? 7 : 6;   // rows from the gather to the collision
   const InstDev I = g.inst[wi.inst];
@@ -443,9 +444,11 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
   // collision LAG iterations later.  The row loop is unrolled PER times so that every slot
   // index is a constant: the carried rows need no register moves, and the next row is
   // gathered straight into its slot (PER = LAG + 2, so that slot is not the one the
-  // collision reads).  With the populations in registers (REGF) the moments of a row are
-  // summed again from them where they are needed (the same sums in the same order, so the
-  // same values) instead of being carried: that keeps the budget at three waves per SIMD.
+  // collision reads).  With the populations in registers (REGF) the moments summed in
+  // stage A go to this lane's own column of an LDS ring (mring), slot by slot like fd, and
+  // stages C and D read them back instead of summing them again: registers alone would
+  // not hold them at three waves per SIMD.  No other lane reads them, so no barrier
+  // orders them.
   constexpr int PER = LAG + 2;
   constexpr int MS = REGF ? 1 : PER;
   R sg_s[MS], jz_s[MS], jr_s[MS], kap_d[5];
@@ -473,9 +476,12 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
 
   R fa[9], fg[9];
   // moments of the row in slot sl
+  auto mom = [&](int sl, int q) -> R& { return mring[(sl * 3 + q) * W + lane]; };
   auto carried = [&](int sl, R& sg, R& jz, R& jr) {
     if (REGF) {
-      moments(fd[REGF ? sl : 0], sg, jz, jr);
+      sg = mom(sl, 0);
+      jz = mom(sl, 1);
+      jr = mom(sl, 2);
     } else {
       sg = sg_s[REGF ? 0 : sl];
       jz = jz_s[REGF ? 0 : sl];
@@ -562,6 +568,10 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
           sg_s[REGF ? 0 : S0] = sg;
           jz_s[REGF ? 0 : S0] = jz;
           jr_s[REGF ? 0 : S0] = jr;
+        } else {
+          mom(S0, 0) = sg;
+          mom(S0, 1) = jz;
+          mom(S0, 2) = jr;
         }
         kap_d[0] = R(kap);
       } else if (a_hi == nr && x == nr) {
@@ -773,6 +783,7 @@ __attribute__((amdgpu_waves_per_eu(SweepWaves<R, PERSIST, REGF, MID>::value))) k
   constexpr int HALO = MID ? 7 : 6;
   __shared__ R ring[RD][W + 4][NRING];
   __shared__ R hring[MID ? 3 * (W + 2) * 3 : 1];
+  __shared__ R mring[REGF && !MOMENTS ? (MID ? 9 : 8) * 3 * W : 1];  // moments, slot by slot
   __shared__ int s_ticket;
   const int lane = threadIdx.x;
   char* const lds = reinterpret_cast<char*>(&ring[0][0][0]);
@@ -790,7 +801,7 @@ __attribute__((amdgpu_waves_per_eu(SweepWaves<R, PERSIST, REGF, MID>::value))) k
     const int need = wi.k0 + wi.ncols == ip->nz ? max(wi.ncols + 2 * HALO, ip->pitch - wi.k0 + HALO)
                                                 : wi.ncols + 2 * HALO;
     if (__builtin_amdgcn_readfirstlane(lane >> 6) * 64 >= need) return;
-    run_item<R, W, MOMENTS, REGF, GUO, MID>(g, wi, lds, hring, lane);
+    run_item<R, W, MOMENTS, REGF, GUO, MID>(g, wi, lds, hring, mring, lane);
     return;
   }
   for (;;) {
@@ -799,7 +810,7 @@ __attribute__((amdgpu_waves_per_eu(SweepWaves<R, PERSIST, REGF, MID>::value))) k
     const int item = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform across the workgroup
     lds_barrier();
     if (item >= g.n_items) break;
-    run_item<R, W, MOMENTS, REGF, GUO, MID>(g, g.items[item], lds, hring, lane);
+    run_item<R, W, MOMENTS, REGF, GUO, MID>(g, g.items[item], lds, hring, mring, lane);
   }
   if (lane == 0) {
     // The last workgroup out rewinds the queue for the next launch (no memset needed,
