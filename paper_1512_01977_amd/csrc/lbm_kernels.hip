@@ -32,7 +32,13 @@
 namespace lbm {
 
 constexpr int RD = 5;  // ring depth: a radius-2 stencil reads 5 consecutive rows
-enum { R_PSI = 0, R_DZ = 1, R_DR = 2, R_UZ = 3, R_UR = 4, NRING = 5 };
+enum { R_PSI = 0, R_DZ = 1, R_DR = 2, R_UZ = 3, R_UR = 4, NRING = 5, R_FKZ = 5, R_FKR = 6 };
+// Fields of the LDS rings: five, and two more (F_K) in FP64 with the populations in registers
+// (run_item's LEAN form).
+template <typename R, bool MOMENTS, bool REGF, bool MID>
+constexpr int ring_fields() {
+  return REGF && sizeof(R) == 8 && !MID && !MOMENTS ? 7 : NRING;
+}
 enum { ERR_BIT_DOMAIN = 1, ERR_BIT_NONFINITE = 2 };
 
 __device__ __forceinline__ int wrapi(int x, int n) {
@@ -249,13 +255,14 @@ __device__ __forceinline__ void shifted_equilibrium(R rho, R sg, R uz, R ur, R e
 // [s][c][q], so the five fields of one column are adjacent and a whole row of
 // stencil reads (columns lane .. lane + 4) lies within 100 bytes of one base.  Every
 // access is one per-lane base plus the uniform slot offset (rb = s * ROWB) plus an
-// immediate; lanes step NRING elements apart, an odd dword stride (no bank conflicts).
-template <typename R, int W>
+// immediate; lanes step NF elements apart (NF = 5: an odd dword stride in FP32, no bank
+// conflicts).
+template <typename R, int W, int NF = NRING>
 struct Rings {
-  static constexpr int ROWB = (W + 4) * NRING * (int)sizeof(R);
+  static constexpr int ROWB = (W + 4) * NF * (int)sizeof(R);
   char* base;  // the ring array; rows are addressed by per-lane byte offsets (lane part included)
   __device__ __forceinline__ R& at(int q, int vb, int dz) const {
-    return *reinterpret_cast<R*>(base + vb + ((2 + dz) * NRING + q) * (int)sizeof(R));
+    return *reinterpret_cast<R*>(base + vb + ((2 + dz) * NF + q) * (int)sizeof(R));
   }
 };
 
@@ -266,8 +273,8 @@ struct Rows5 {
 
 // D_z g (eq. fifthorderaccuratefinitedifference): directions 1, 3, 5, 6, 7, 8, each
 // 8 g(x + c_i) - g(x + 2 c_i) weighted by c_iz; unscaled (the caller multiplies by 1/36).
-template <typename R, int W>
-__device__ __forceinline__ R stencil_dz36(const Rings<R, W>& L, int q, const Rows5& r) {
+template <typename R, int W, int NF>
+__device__ __forceinline__ R stencil_dz36(const Rings<R, W, NF>& L, int q, const Rows5& r) {
   const R a = (L.at(q, r.s0, 1) - L.at(q, r.s0, -1)) + (L.at(q, r.p1, 1) - L.at(q, r.p1, -1)) +
               (L.at(q, r.m1, 1) - L.at(q, r.m1, -1));
   const R b = (L.at(q, r.s0, 2) - L.at(q, r.s0, -2)) + (L.at(q, r.p2, 2) - L.at(q, r.p2, -2)) +
@@ -276,8 +283,8 @@ __device__ __forceinline__ R stencil_dz36(const Rings<R, W>& L, int q, const Row
 }
 
 // D_r g: directions 2, 4, 5, 6, 7, 8 weighted by c_ir; unscaled.
-template <typename R, int W>
-__device__ __forceinline__ R stencil_dr36(const Rings<R, W>& L, int q, const Rows5& r) {
+template <typename R, int W, int NF>
+__device__ __forceinline__ R stencil_dr36(const Rings<R, W, NF>& L, int q, const Rows5& r) {
   const R a = (L.at(q, r.p1, -1) + L.at(q, r.p1, 0) + L.at(q, r.p1, 1)) -
               (L.at(q, r.m1, -1) + L.at(q, r.m1, 0) + L.at(q, r.m1, 1));
   const R b = (L.at(q, r.p2, -2) + L.at(q, r.p2, 0) + L.at(q, r.p2, 2)) -
@@ -425,15 +432,22 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
   const R psi_ref = R(I.psi_ref), pr2 = R(2.0 * I.psi_ref);
   const bool guo = GUO && I.forcing == LBM_FORCING_GUO;
   const bool mid = MID && I.source_mid != 0;
-  const Rings<R, W> L{lds};
-  constexpr int ROWB = Rings<R, W>::ROWB;
+  // LEAN (FP64 with the populations in registers, node source): F_K travels from stage B to
+  // stage C in two more ring fields (in the slot of its row, which no later row takes over
+  // before stage C reads it), and kappa and 1/r are computed again where they are used (the
+  // same expressions, so the same values): that frees the 24 VGPRs that let the carried
+  // populations fit two waves per SIMD (251 VGPRs and 73 KB of LDS at W 256).
+  constexpr bool LEAN = REGF && sizeof(R) == 8 && !MID && !MOMENTS;
+  constexpr int NF = ring_fields<R, MOMENTS, REGF, MID>();
+  const Rings<R, W, NF> L{lds};
+  constexpr int ROWB = Rings<R, W, NF>::ROWB;
   constexpr R i36 = R(1.0 / 36.0);
 
   // rb[k] = this lane's byte offset in the ring slot holding row t - k (slot = row mod 5);
   // stepping t rotates the five offsets by one.  They are carried per lane so that each
   // ring access is a single base register plus an immediate.
   int rb[5];
-  const int lane_off = lane * NRING * (int)sizeof(R);
+  const int lane_off = lane * NF * (int)sizeof(R);
 #pragma unroll
   for (int k = 0; k < 5; ++k) rb[k] = lane_off + slot(a_lo - k) * ROWB;
 
@@ -444,11 +458,12 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
   // collision LAG iterations later.  The row loop is unrolled PER times so that every slot
   // index is a constant: the carried rows need no register moves, and the next row is
   // gathered straight into its slot (PER = LAG + 2, so that slot is not the one the
-  // collision reads).  With the populations in registers (REGF) the moments summed in
-  // stage A go to this lane's own column of an LDS ring (mring), slot by slot like fd, and
-  // stages C and D read them back instead of summing them again: registers alone would
-  // not hold them at three waves per SIMD.  No other lane reads them, so no barrier
-  // orders them.
+  // collision reads).  With the populations in registers (REGF) in FP32 the moments summed
+  // in stage A go to this lane's own column of an LDS ring (mring), slot by slot like fd,
+  // and stages C and D read them back instead of summing them again: registers alone would
+  // not hold them at three waves per SIMD.  No other lane reads them, so no barrier orders
+  // them.  FP64 sums them again from the carried populations (the same sums in the same
+  // order): its LDS goes to the LEAN ring fields.
   constexpr int PER = LAG + 2;
   constexpr int MS = REGF ? 1 : PER;
   R sg_s[MS], jz_s[MS], jr_s[MS], kap_d[5];
@@ -478,10 +493,12 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
   // moments of the row in slot sl
   auto mom = [&](int sl, int q) -> R& { return mring[(sl * 3 + q) * W + lane]; };
   auto carried = [&](int sl, R& sg, R& jz, R& jr) {
-    if (REGF) {
+    if (REGF && sizeof(R) == 4) {
       sg = mom(sl, 0);
       jz = mom(sl, 1);
       jr = mom(sl, 2);
+    } else if (REGF) {
+      moments(fd[REGF ? sl : 0], sg, jz, jr);
     } else {
       sg = sg_s[REGF ? 0 : sl];
       jz = jz_s[REGF ? 0 : sl];
@@ -568,12 +585,12 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
           sg_s[REGF ? 0 : S0] = sg;
           jz_s[REGF ? 0 : S0] = jz;
           jr_s[REGF ? 0 : S0] = jr;
-        } else {
+        } else if (sizeof(R) == 4) {
           mom(S0, 0) = sg;
           mom(S0, 1) = jz;
           mom(S0, 2) = jr;
         }
-        kap_d[0] = R(kap);
+        if (!LEAN) kap_d[0] = R(kap);
       } else if (a_hi == nr && x == nr) {
         L.at(R_PSI, rb[0], 0) = L.at(R_PSI, rb[1], 0);  // even at the wall: row nr = row nr - 1
       } else if (a_hi == nr && x == nr + 1) {
@@ -587,8 +604,8 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
       const int x = t - 2;
       if (x >= b_lo && x < b_hi) {
         const Rows5 r{rb[4], rb[3], rb[2], rb[1], rb[0]};
-        const R dz = stencil_dz36<R, W>(L, R_PSI, r) * i36;
-        const R dr = stencil_dr36<R, W>(L, R_PSI, r) * i36;
+        const R dz = stencil_dz36(L, R_PSI, r) * i36;
+        const R dr = stencil_dr36(L, R_PSI, r) * i36;
         // F_K = 6 [A sum_i w_i psi_i^2 c_i + (1 - 2A) psi sum_i w_i psi_i c_i], i = 1, 2, ..., 8
         const R w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
         const R q1 = L.at(R_PSI, r.s0, 1), q2 = L.at(R_PSI, r.p1, 0), q3 = L.at(R_PSI, r.s0, -1);
@@ -602,8 +619,13 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         const R s2z = w1 * (t1 - t3) + w2 * ((t5 - t7) + (t8 - t6));
         const R s2r = w1 * (t2 - t4) + w2 * ((t5 - t7) - (t8 - t6));
         const R bpsi = B6 * (psi_ref + L.at(R_PSI, r.s0, 0));
-        fk0z = fmad(A6, s2z, bpsi * s1z);
-        fk0r = fmad(A6, s2r, bpsi * s1r);
+        if (LEAN) {
+          L.at(R_FKZ, r.s0, 0) = fmad(A6, s2z, bpsi * s1z);
+          L.at(R_FKR, r.s0, 0) = fmad(A6, s2r, bpsi * s1r);
+        } else {
+          fk0z = fmad(A6, s2z, bpsi * s1z);
+          fk0r = fmad(A6, s2r, bpsi * s1r);
+        }
         L.at(R_DZ, r.s0, 0) = dz;
         L.at(R_DR, r.s0, 0) = dr;
         if (x == 0) { L.at(R_DZ, rb[3], 0) = dz; L.at(R_DR, rb[3], 0) = -dr; }  // row -1 = row t - 3
@@ -625,14 +647,20 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         const Rows5 r{rb[1], rb[0], rb[4], rb[3], rb[2]};
         R sg4, jz, jr;
         carried(S4, sg4, jz, jr);
-        const R rho = rho_ref + sg4, kap = kap_d[4];
-        R fz = fk2z, fr = fk2r;
+        const R rho = rho_ref + sg4;
+        R kap = kap_d[4];
+        if (LEAN) {
+          double Pk_, kap_;
+          eos_dev(I, I.rho_ref + (double)sg4, Pk_, kap_);
+          kap = R(kap_);
+        }
+        R fz = LEAN ? L.at(R_FKZ, r.s0, 0) : fk2z, fr = LEAN ? L.at(R_FKR, r.s0, 0) : fk2r;
         if (I.axisym) {
           // F_axis = 3K/r [psi D_rz psi + 6A D_r psi D_z psi, psi (D_rr psi - D_r psi / r) + 6A (D_r psi)^2]
-          const R drr = stencil_dr36<R, W>(L, R_DR, r) * i36;
-          const R drz = stencil_dr36<R, W>(L, R_DZ, r) * i36;
+          const R drr = stencil_dr36(L, R_DR, r) * i36;
+          const R drz = stencil_dr36(L, R_DZ, r) * i36;
           const R psi = psi_ref + L.at(R_PSI, r.s0, 0), dz = L.at(R_DZ, r.s0, 0), dr = L.at(R_DR, r.s0, 0);
-          const R ir = recip(R(x) + R(0.5));  // 1/r_j (uniform), carried on to stage D
+          const R ir = recip(R(x) + R(0.5));  // 1/r_j (uniform), carried on to stage D unless LEAN
           ir0 = ir;
           const R k3 = (I.faxis_sound ? R(1.0 / 3.0) : R(3) * kap * kap) * ir;
           const R a6dr = A6 * dr;
@@ -680,10 +708,10 @@ __device__ __forceinline__ void run_item(const SweepArgs<R>& g, const WorkItem w
         carried(S6, sg6, jz6, jr6);
         const R rho = rho_ref + sg6;
         const R uz = L.at(R_UZ, r.s0, 0), ur = L.at(R_UR, r.s0, 0);
-        const R druz = stencil_dr36<R, W>(L, R_UZ, r);  // 36 D_r u_z
-        const R dzur = stencil_dz36<R, W>(L, R_UR, r);  // 36 D_z u_r
-        const R drur = stencil_dr36<R, W>(L, R_UR, r);  // 36 D_r u_r
-        const R ir = ir2;
+        const R druz = stencil_dr36(L, R_UZ, r);  // 36 D_r u_z
+        const R dzur = stencil_dz36(L, R_UR, r);  // 36 D_z u_r
+        const R drur = stencil_dr36(L, R_UR, r);  // 36 D_r u_r
+        const R ir = LEAN ? recip(R(x) + R(0.5)) : ir2;
         const R mu36 = rho * nu * i36;
         const R ir3 = R(3) * ir;
         const R rur = rho * ur;
@@ -760,18 +788,18 @@ __device__ __forceinline__ int xcd_map(int b, int G) {
   return xcd < rem ? xcd * (q + 1) + pos : rem * (q + 1) + (xcd - rem) * q + pos;
 }
 
-// Minimum waves per SIMD asked of the register allocator (170 VGPRs for three waves in FP32,
-// 256 for two in FP64).  The budget must not force spills: a spill reload goes through the
-// vector memory counter and would make the wave wait for its prefetched rows.  The
-// persistent loop keeps more state live and the variants that carry the populations in
-// registers need more; they get one wave less, or take what they need.
-// The link-midpoint source (MID) keeps more values live: three waves in FP32 and two in
-// FP64 when gathering again, two and one with the populations in registers.
+// Minimum waves per SIMD asked of the register allocator (168 VGPRs for three waves, 256 for
+// two): three in FP32, two in FP64 (with the populations in registers, FP64 fits two only
+// through run_item's LEAN form).  The budget must not force spills: a spill reload goes
+// through the vector memory counter and would make the wave wait for its prefetched rows.
+// The persistent loop keeps more state live: one wave less.  The link-midpoint source (MID)
+// keeps more values live: three waves in FP32 and two in FP64 when gathering again, two and
+// one with the populations in registers.
 template <typename R, bool PERSIST, bool REGF, bool MID>
 struct SweepWaves {
-  static constexpr int base = REGF ? (sizeof(R) == 4 ? 3 : 1) : (sizeof(R) == 4 ? 3 : 2);
+  static constexpr int base = sizeof(R) == 4 ? 3 : 2;
   static constexpr int mid = REGF ? (sizeof(R) == 4 ? 2 : 1) : (sizeof(R) == 4 ? 3 : 2);
-  static constexpr int value = MID ? mid : (PERSIST && !REGF) ? base - 1 : base;
+  static constexpr int value = MID ? mid : PERSIST ? base - 1 : base;
 };
 
 // GUO: some instance of the launch uses Guo's forcing (a per-instance branch); otherwise
@@ -781,9 +809,9 @@ template <typename R, int W, bool MOMENTS, bool PERSIST, bool REGF, bool GUO, bo
 __global__ void __launch_bounds__(W)
 __attribute__((amdgpu_waves_per_eu(SweepWaves<R, PERSIST, REGF, MID>::value))) k_sweep(SweepArgs<R> g) {
   constexpr int HALO = MID ? 7 : 6;
-  __shared__ R ring[RD][W + 4][NRING];
+  __shared__ R ring[RD][W + 4][ring_fields<R, MOMENTS, REGF, MID>()];
   __shared__ R hring[MID ? 3 * (W + 2) * 3 : 1];
-  __shared__ R mring[REGF && !MOMENTS ? (MID ? 9 : 8) * 3 * W : 1];  // moments, slot by slot
+  __shared__ R mring[REGF && !MOMENTS && sizeof(R) == 4 ? (MID ? 9 : 8) * 3 * W : 1];  // moments, slot by slot
   __shared__ int s_ticket;
   const int lane = threadIdx.x;
   char* const lds = reinterpret_cast<char*>(&ring[0][0][0]);
