@@ -101,7 +101,9 @@ typedef struct {
                            first, the strips of one row band on one XCD (their shared edge
                            lines stay in its L2); other values: LBM_ERR_ARG.  Ignored by the
                            persistent grid, which always takes items longest first */
-  int32_t regf;         /* 1: carry gathered populations in registers (no second gather) */
+  int32_t regf;         /* 1: carry gathered populations in registers (no second gather; the
+                           default except in FP64 with the link-midpoint source); 0: gather
+                           them again for the collision.  Both give the same results */
   int32_t streams;      /* 1 (or 0): one launch per step for all instances; 2..4: the instances
                            of a batch split into this many groups of about equal node counts,
                            each stepped by its own launches on its own stream (created by the

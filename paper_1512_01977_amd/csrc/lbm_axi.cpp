@@ -168,8 +168,11 @@ bool valid_width(int w) { return w == 64 || w == 128 || w == 256; }
 
 // Default shape without timing anything: minimise max(total lane-iterations / lanes the chip
 // keeps in flight, longest item / 3), the second term being the chain of one work item when
-// the chip is under-filled (its waves then run about three times faster).
+// the chip is under-filled (its waves then run about three times faster).  The populations
+// ride in registers (fewer bytes, the same results), except in FP64 with the link-midpoint
+// source, whose register form fits only one wave per SIMD.
 lbm_axi_launch default_launch(const lbm_axi_s* h) {
+  const int regf = h->prec == LBM_PREC_FP32 || !h->any_mid ? 1 : 0;
   lbm_axi_launch best{};
   double best_t = 1e300;
   const double cap = (double)h->cus * 4 * 64 * 3;
@@ -183,7 +186,7 @@ lbm_axi_launch default_launch(const lbm_axi_s* h) {
       const double t = std::max((double)lane_iters / cap, longest / 3.0);
       if (t < best_t * 0.999) {
         best_t = t;
-        best = lbm_axi_launch{w, sg, h->n > 1 ? 1 : 0, 0, 1, 0, 1};
+        best = lbm_axi_launch{w, sg, h->n > 1 ? 1 : 0, 0, 1, regf, 1};
       }
     }
   return best;

@@ -123,6 +123,23 @@ def test_fp32_form_launch_shapes_agree_bitwise():
                 assert np.array_equal(a, b), launch
 
 
+def test_fp64_form_launch_shapes_agree_bitwise():
+    # FP64: the populations carried in registers (F_K then travels through the LDS rings and
+    # kappa and 1/r are computed again, the same expressions) or gathered again for the
+    # collision, persistent or not, any strip width and segment length: the same arithmetic
+    # on every node, so bitwise the same state; the first shape is also checked against the
+    # oracle.
+    d = base(150, 37, A=-0.152, tau=0.9)
+    rho0 = droplet_rho(d, 11.0, eps=0.2, zc=70.0)
+    o, first = run_pair(d, rho0, 120, precision=0, launch=LAUNCHES[0])
+    assert_fp64_parity(o, first)
+    for launch in LAUNCHES[1:]:
+        print("case", launch, flush=True)
+        g = run_pair_gpu(d, rho0, 120, 0, launch)
+        for a, b in zip(g, first):
+            assert np.array_equal(a, b), launch
+
+
 def run_pair_gpu(d, rho0, steps, precision, launch):
     L = lbm()
     with L.LbmAxi(gpu_params(d), rho0, precision=precision) as sim:
