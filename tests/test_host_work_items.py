@@ -1,5 +1,5 @@
 """CPU checks of the step kernel's work lists as the library builds them (the host code in
-paper_1512_01977_amd/csrc/work_items.h, compiled here into a small driver): the items of a
+paper_1512_01977_amd/csrc/work_items.h, compiled into a small test program): the items of a
 launch cover every node of every instance exactly once, strips are whole 128-byte lines,
 segments respect the 2 GiB descriptor cap, each item order keeps its promise, and a batch
 split into stream groups gives every instance to one group with balanced node counts."""
@@ -14,7 +14,7 @@ XCDS = 8
 
 
 @pytest.fixture(scope="module")
-def driver(tmp_path_factory):
+def lister(tmp_path_factory):
     exe = str(tmp_path_factory.mktemp("work_items") / "check")
     cmd = ["hipcc", "-std=c++17", "-O1", "-I" + os.path.join(ROOT, "include"),
            "-I" + os.path.join(ROOT, "paper_1512_01977_amd", "csrc"),
@@ -23,10 +23,10 @@ def driver(tmp_path_factory):
     return exe
 
 
-def work_list(driver, esize, width, seg, persistent, xcd, streams, members):
+def work_list(lister, esize, width, seg, persistent, xcd, streams, members):
     spec = f"{esize} {width} {seg} {persistent} {xcd} {streams} {len(members)}\n" + \
            "".join(f"{nz} {nr}\n" for nz, nr in members)
-    out = subprocess.run([driver], input=spec, capture_output=True, text=True, check=True).stdout.split("\n")
+    out = subprocess.run([lister], input=spec, capture_output=True, text=True, check=True).stdout.split("\n")
     groups = [tuple(map(int, out[g].split())) for g in range(streams)]
     items = np.array([list(map(int, l.split())) for l in out[streams:] if l.strip()], dtype=np.int64)
     return groups, items.reshape(-1, 5)
@@ -36,8 +36,8 @@ def cost(it):  # rows swept by an item, pipeline rows included (the order key)
     return (it[:, 4] - it[:, 3]) + np.minimum(6, it[:, 3]) + 6
 
 
-def check_list(driver, esize, width, seg, persistent, xcd, streams, members):
-    groups, items = work_list(driver, esize, width, seg, persistent, xcd, streams, members)
+def check_list(lister, esize, width, seg, persistent, xcd, streams, members):
+    groups, items = work_list(lister, esize, width, seg, persistent, xcd, streams, members)
     line = 128 // esize
     wout = (width - 12) // line * line
     # seven halo lanes on either side (the link-midpoint source's pipeline) fit as well
@@ -103,24 +103,24 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"s{c[0]}w{c[1]}g{c[2]}p{c[3]}x{c[4]}n{c[5]}")
-def test_work_list_properties(driver, case):
-    check_list(driver, *case)
+def test_work_list_properties(lister, case):
+    check_list(lister, *case)
 
 
-def test_benchmark_ensemble_work_list(driver):
+def test_benchmark_ensemble_work_list(lister):
     # the 256-member ensemble in the benchmark's shape (two stream groups, row bands on one
     # XCD) and in one launch longest first
     from paper_1512_01977_amd import inputs
     members = [(m.nz, m.nr) for m in inputs.ensemble(n=256, seed=151201977, tau_lo=0.7)]
     assert sum(nz * nr for nz, nr in members) == 12_889_106
-    _, items = check_list(driver, 4, 256, 64, 0, 2, 2, members)
-    check_list(driver, 4, 128, 112, 0, 0, 1, members)
+    _, items = check_list(lister, 4, 256, 64, 0, 2, 2, members)
+    check_list(lister, 4, 128, 112, 0, 0, 1, members)
     assert len(items) > 1000
 
 
-def test_segment_cap_for_wide_fp64_rows(driver):
+def test_segment_cap_for_wide_fp64_rows(lister):
     # 16384-wide FP64 rows (pitch 16400 with the padding line): a row block is 1.18 MB, so a
     # work item may span at most 2^31 / (9 * 16400 * 8) - 16 = 1802 rows; whole-column segments
     # are split there.
-    _, items = check_list(driver, 8, 256, 0, 0, 1, 1, [(16384, 4000)])
+    _, items = check_list(lister, 8, 256, 0, 0, 1, 1, [(16384, 4000)])
     assert (items[:, 4] - items[:, 3]).max() == 1802
