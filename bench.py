@@ -249,8 +249,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the method's single-GPU kernel is what this "
-              "build provides (no multi-GPU path); run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library steps each domain on one GPU and has "
+              "no multi-GPU path; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
