@@ -793,12 +793,12 @@ __device__ __forceinline__ int xcd_map(int b, int G) {
 // through run_item's LEAN form).  The budget must not force spills: a spill reload goes
 // through the vector memory counter and would make the wave wait for its prefetched rows.
 // The persistent loop keeps more state live: one wave less.  The link-midpoint source (MID)
-// keeps more values live: three waves in FP32 and two in FP64 when gathering again, two and
-// one with the populations in registers.
+// keeps more values live: in FP32 two waves with the populations in registers, three when
+// gathering again (two for the persistent loop); in FP64 one.
 template <typename R, bool PERSIST, bool REGF, bool MID>
 struct SweepWaves {
   static constexpr int base = sizeof(R) == 4 ? 3 : 2;
-  static constexpr int mid = REGF ? (sizeof(R) == 4 ? 2 : 1) : (sizeof(R) == 4 ? 3 : 2);
+  static constexpr int mid = sizeof(R) == 8 ? 1 : REGF ? 2 : PERSIST ? 2 : 3;
   static constexpr int value = MID ? mid : PERSIST ? base - 1 : base;
 };
 
