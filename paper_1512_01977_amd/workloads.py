@@ -1,7 +1,9 @@
 """Named synthetic workloads (the paper's validation set-ups, Sec. 3, at the sizes
 the benchmark and the tests use).  Parameters only: temperatures are set from
-T/T_c and initial densities from the Maxwell coexistence densities, both through
-the library's host EOS helpers; fields come from the seeded input module.
+T/T_c and initial densities from the Maxwell coexistence densities, both through an EOS
+helper (`eos`: the library's host helpers by default; tests that compare with the CPU
+oracle pass the oracle's own, so that none of the oracle's inputs comes from the library);
+fields come from the seeded input module.
 
 Carnahan-Starling coefficients a = 1, b = 4, R = 1 throughout.  The pressure
 scale lambda and the mixing parameter A are the paper's own knobs (Sec. 2.3):
@@ -38,56 +40,63 @@ class Workload:
         return int(sum(p.nz * p.nr for p in self.params))
 
 
-def cs_params(nz, nr, t_reduced, tau, lam=1.0, A=0.0, bc_top=TOP_FREE_SLIP, axisym=1) -> Params:
+class LibraryEOS:
+    """Critical point (rho_c, T_c, P_c) and Maxwell densities (rho_v, rho_l, P_sat) of the
+    EOS in a Params, from the library's host helpers."""
+    critical = staticmethod(lbm_axi_eos_critical)
+    coexistence = staticmethod(lbm_axi_eos_coexistence)
+
+
+def cs_params(nz, nr, t_reduced, tau, lam=1.0, A=0.0, bc_top=TOP_FREE_SLIP, axisym=1, eos=None) -> Params:
     p = Params(nz=nz, nr=nr, tau=tau, eos=EOS_CS, eos_a=1.0, eos_b=4.0, eos_R=1.0, lam=lam, A=A,
                axisym=axisym, bc_top=bc_top)
-    _, Tc, _ = lbm_axi_eos_critical(p)
+    _, Tc, _ = (eos or LibraryEOS).critical(p)
     p.T = t_reduced * Tc
     return p
 
 
-def coexistence(p: Params):
-    rv, rl, _ = lbm_axi_eos_coexistence(p)
+def coexistence(p: Params, eos=None):
+    rv, rl, _ = (eos or LibraryEOS).coexistence(p)
     return rv, rl
 
 
-def static_droplet(precision=PREC_FP64) -> Workload:
+def static_droplet(precision=PREC_FP64, eos=None) -> Workload:
     """128 x 64, T/T_c = 0.8, tau = 1, R = 20 on the axis, width-5 tanh, noise 1e-4 (seed 1)."""
-    p = cs_params(128, 64, 0.8, 1.0)
-    rv, rl = coexistence(p)
+    p = cs_params(128, 64, 0.8, 1.0, eos=eos)
+    rv, rl = coexistence(p, eos)
     rho = inputs.droplet(128, 64, rv, rl, 20.0, zc=64.0, width=5.0, noise=1e-4, seed=1)
     return Workload("static_droplet_128x64", [p], [rho], precision, 2000,
                     dict(R=20.0, zc=64.0, rho_v=rv, rho_l=rl))
 
 
-def mode2_droplet(precision=PREC_FP64, nz=1024, nr=512, radius=100.0) -> Workload:
+def mode2_droplet(precision=PREC_FP64, nz=1024, nr=512, radius=100.0, eos=None) -> Workload:
     """Mode-2 oscillation at density ratio ~1e3: T/T_c = 0.485, tau = 0.8, P2 amplitude 0.05."""
-    p = cs_params(nz, nr, 0.485, 0.8, lam=0.05, A=-0.152)
-    rv, rl = coexistence(p)
+    p = cs_params(nz, nr, 0.485, 0.8, lam=0.05, A=-0.152, eos=eos)
+    rv, rl = coexistence(p, eos)
     rho = inputs.droplet(nz, nr, rv, rl, radius, zc=nz / 2, width=10.0, eps=0.05, noise=1e-4,
                          seed=2)
     return Workload(f"mode2_droplet_{nz}x{nr}", [p], [rho], precision, 20000,
                     dict(R=radius, zc=nz / 2, rho_v=rv, rho_l=rl))
 
 
-def density_wave(precision=PREC_FP64, nz=4096, nr=2048) -> Workload:
+def density_wave(precision=PREC_FP64, nz=4096, nr=2048, eos=None) -> Workload:
     """Single-phase vapour at T/T_c = 0.9 with a radial cosine of amplitude 1e-2, wavelength
     256, noise 1e-6 (seed 3), tau = 0.7, no-slip wall at r = nr (Sec. 3.3)."""
-    p = cs_params(nz, nr, 0.9, 0.7, bc_top=TOP_NO_SLIP)
-    rv, _ = coexistence(p)
+    p = cs_params(nz, nr, 0.9, 0.7, bc_top=TOP_NO_SLIP, eos=eos)
+    rv, _ = coexistence(p, eos)
     rho = inputs.radial_wave(nz, nr, rv, amplitude=1e-2, wavelength=256.0, noise=1e-6, seed=3)
     return Workload(f"density_wave_{nz}x{nr}", [p], [rho], precision, 10000, dict(rho_g=rv))
 
 
-def ensemble(precision=PREC_FP32, n=256, seed=151201977) -> Workload:
+def ensemble(precision=PREC_FP32, n=256, seed=151201977, eos=None) -> Workload:
     """Uneven droplet batch: nr ~ U{32..256}, nz = 2 nr, T/T_c ~ U[0.55, 0.9],
     tau ~ U[0.7, 1.2], R = 0.3 nr, odd members with a P2 perturbation of 0.05.  (tau below 0.7
     at T/T_c near 0.55 leaves the real-psi range during the first hundred steps, in the CPU
     oracle as well.)"""
     params, rhos, meta = [], [], []
     for ins in inputs.ensemble(n=n, seed=seed, tau_lo=0.7):
-        p = cs_params(ins.nz, ins.nr, ins.t_reduced, ins.tau, lam=0.05, A=-0.152)
-        rv, rl = coexistence(p)
+        p = cs_params(ins.nz, ins.nr, ins.t_reduced, ins.tau, lam=0.05, A=-0.152, eos=eos)
+        rv, rl = coexistence(p, eos)
         rhos.append(inputs.droplet(ins.nz, ins.nr, rv, rl, ins.radius, zc=ins.nz / 2, width=10.0,
                                    eps=ins.eps, noise=1e-4, seed=ins.noise_seed))
         params.append(p)
@@ -95,11 +104,11 @@ def ensemble(precision=PREC_FP32, n=256, seed=151201977) -> Workload:
     return Workload(f"droplet_ensemble_{n}", params, rhos, precision, 2000, dict(members=meta))
 
 
-def large_droplet(precision=PREC_FP32, nz=16384, nr=8192, radius=2000.0) -> Workload:
+def large_droplet(precision=PREC_FP32, nz=16384, nr=8192, radius=2000.0, eos=None) -> Workload:
     """16384 x 8192 (134M nodes), ratio ~1e3 droplet R = 2000 with P2 amplitude 0.02,
     tau = 0.8, noise 1e-4 (seed 5)."""
-    p = cs_params(nz, nr, 0.485, 0.8, lam=0.05, A=-0.152)
-    rv, rl = coexistence(p)
+    p = cs_params(nz, nr, 0.485, 0.8, lam=0.05, A=-0.152, eos=eos)
+    rv, rl = coexistence(p, eos)
     rho = inputs.droplet(nz, nr, rv, rl, radius, zc=nz / 2, width=10.0, eps=0.02, noise=1e-4,
                          seed=5)
     return Workload(f"large_droplet_{nz}x{nr}", [p], [rho], precision, 5000,

@@ -36,6 +36,27 @@ def gpu_params(d):
     return lbm.Params(**d)
 
 
+def oparams(p) -> O.Params:
+    """The oracle's parameter object for a binding Params (the same fields)."""
+    return O.Params(nz=p.nz, nr=p.nr, tau=p.tau, eos=p.eos, T=p.T, eos_a=p.eos_a, eos_b=p.eos_b,
+                    eos_R=p.eos_R, lam=p.lam, A=p.A, axisym=p.axisym, faxis_sound=p.faxis_sound,
+                    bc_top=p.bc_top, gz=p.gz, forcing=p.forcing, source_mid=p.source_mid)
+
+
+class OracleEOS:
+    """Critical point and Maxwell densities from the oracle: the EOS helper of the named
+    workloads in tests that compare with the oracle, so that none of its inputs comes from
+    the library."""
+
+    @staticmethod
+    def critical(p):
+        return O.critical(oparams(p))
+
+    @staticmethod
+    def coexistence(p):
+        return O.coexistence(oparams(p))
+
+
 def droplet_rho(d, radius, eps=0.0, noise=1e-4, seed=1, width=5.0, zc=None):
     if d["eos"] == O.EOS_IDEAL:
         r = inputs.radial_wave(d["nz"], d["nr"], 1.0, amplitude=0.05, wavelength=d["nr"] / 1.5,

@@ -21,7 +21,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from test_gpu_fullsize import oparams
+from cases import OracleEOS, oparams
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def lbm():
 def test_ensemble_members_laplace_2000_steps():
     L = lbm()
     from paper_1512_01977_amd import workloads
-    wl = workloads.ensemble(precision=L.PREC_FP32)
+    wl = workloads.ensemble(precision=L.PREC_FP32, eos=OracleEOS)
     pick = [k for k, p in enumerate(wl.params) if p.nz * p.nr <= 20000][:6]
     assert len(pick) == 6
     meta = [wl.meta["members"][k] for k in pick]
@@ -58,7 +58,7 @@ def test_ensemble_members_laplace_2000_steps():
 def test_density_wave_mass_trace_10000_steps():
     L = lbm()
     from paper_1512_01977_amd import workloads
-    wl = workloads.density_wave(precision=L.PREC_FP64, nz=8, nr=2048)
+    wl = workloads.density_wave(precision=L.PREC_FP64, nz=8, nr=2048, eos=OracleEOS)
     p, rho0 = wl.params[0], wl.rho0[0]
     q = oparams(p)
     f = O.init(q, rho0)
@@ -80,8 +80,8 @@ def test_density_wave_mass_trace_10000_steps():
 def test_mode2_ratio_1000_frequency_20000_steps():
     L = lbm()
     from paper_1512_01977_amd import inputs, workloads
-    p = workloads.cs_params(256, 128, 0.485, 0.8, lam=0.05, A=-0.152)
-    rv, rl = workloads.coexistence(p)
+    p = workloads.cs_params(256, 128, 0.485, 0.8, lam=0.05, A=-0.152, eos=OracleEOS)
+    rv, rl = workloads.coexistence(p, OracleEOS)
     rho0 = inputs.droplet(256, 128, rv, rl, 30.0, zc=128.0, width=10.0, eps=0.05, noise=1e-4, seed=2)
     thr = 0.5 * (rv + rl)
     q = oparams(p)

@@ -1,6 +1,7 @@
 """The benchmark workloads at full size, in the launch shapes bench.py times (the shape the
 committed byte counters were taken in, else the tuner's pick), against the oracle on the
-same seeded inputs.
+same seeded inputs (their temperatures and densities set through the oracle's EOS helpers,
+which agree with the library's to rounding).
 
 FP64 is held to the 1e-10 bar of the small-grid parity tests.  The FP32 form's field
 errors against the FP64 oracle are printed and bounded at about ten times what FP32
@@ -13,6 +14,7 @@ import pytest
 
 import bench
 import oracle as O
+from cases import OracleEOS, oparams
 
 pytestmark = pytest.mark.gpu
 
@@ -20,10 +22,6 @@ ENSEMBLE_STEPS = 20
 LARGE_STEPS = 2
 
 
-def oparams(p):
-    return O.Params(nz=p.nz, nr=p.nr, tau=p.tau, eos=p.eos, T=p.T, eos_a=p.eos_a, eos_b=p.eos_b,
-                    eos_R=p.eos_R, lam=p.lam, A=p.A, axisym=p.axisym, faxis_sound=p.faxis_sound,
-                    bc_top=p.bc_top, gz=p.gz, forcing=p.forcing)
 
 
 def oracle_moments(p, rho0, steps):
@@ -63,7 +61,7 @@ def run_gpu(wl, steps, chunk):
 @pytest.fixture(scope="module")
 def ensemble_oracle():
     from paper_1512_01977_amd import workloads
-    wl = workloads.ensemble(precision=0)
+    wl = workloads.ensemble(precision=0, eos=OracleEOS)
     return [oracle_moments(p, r, ENSEMBLE_STEPS) for p, r in zip(wl.params, wl.rho0)]
 
 
@@ -72,7 +70,7 @@ def test_ensemble_full_size_bench_launch(precision, ensemble_oracle):
     # All 256 members (12 889 106 nodes, nr 32..256, ragged strips) after 20 steps run as
     # two 10-step graph replays, in the shape bench.py times for this precision.
     from paper_1512_01977_amd import workloads
-    wl = workloads.ensemble(precision=precision)
+    wl = workloads.ensemble(precision=precision, eos=OracleEOS)
     got = run_gpu(wl, ENSEMBLE_STEPS, 10)
     errs = np.array([field_errors(g, o) for g, o in zip(got, ensemble_oracle)])
     print(f"ensemble precision {precision}: max rho err {errs[:, 0].max():.3e}, "
@@ -86,7 +84,7 @@ def test_ensemble_full_size_bench_launch(precision, ensemble_oracle):
 @pytest.fixture(scope="module")
 def large_oracle():
     from paper_1512_01977_amd import workloads
-    wl = workloads.large_droplet(precision=0)
+    wl = workloads.large_droplet(precision=0, eos=OracleEOS)
     return oracle_moments(wl.params[0], wl.rho0[0], LARGE_STEPS)
 
 
@@ -94,7 +92,7 @@ def large_oracle():
 def test_large_domain_full_size_bench_launch(precision, large_oracle):
     # The 16384 x 8192 droplet (134 217 728 nodes) after two steps, every node.
     from paper_1512_01977_amd import workloads
-    wl = workloads.large_droplet(precision=precision)
+    wl = workloads.large_droplet(precision=precision, eos=OracleEOS)
     (g,) = run_gpu(wl, LARGE_STEPS, 0)
     er, eu = field_errors(g, large_oracle)
     print(f"large precision {precision}: rho err {er:.3e}, u err {eu:.3e}", flush=True)
@@ -112,7 +110,7 @@ def single_oracle():
     from paper_1512_01977_amd import workloads
     out = {}
     for name, steps in SINGLE_STEPS.items():
-        wl = workloads.REGISTRY[name](precision=0)
+        wl = workloads.REGISTRY[name](precision=0, eos=OracleEOS)
         out[name] = oracle_moments(wl.params[0], wl.rho0[0], steps)
     return out
 
@@ -128,7 +126,7 @@ def test_single_domain_workloads_full_size(name, precision, single_oracle):
     # roundoff whatever its own size (the wave starts at rest: after 4 steps its velocity scale
     # is small enough for that to be 2e-4 of it).
     from paper_1512_01977_amd import workloads
-    wl = workloads.REGISTRY[name](precision=precision)
+    wl = workloads.REGISTRY[name](precision=precision, eos=OracleEOS)
     (g,) = run_gpu(wl, SINGLE_STEPS[name], 0)
     er, eu = field_errors(g, single_oracle[name])
     ua = max(float(np.abs(g[1] - single_oracle[name][1]).max()), float(np.abs(g[2] - single_oracle[name][2]).max()))
@@ -146,7 +144,7 @@ def test_fp64_domain_beyond_four_gib_per_three_planes():
     # rebases its descriptors per work item.  Whole-column segments (the segment cap then
     # splits each column), two steps, every node against the oracle.
     from paper_1512_01977_amd import lbm, workloads
-    wl = workloads.large_droplet(precision=0, nz=16384, nr=12288, radius=2500.0)
+    wl = workloads.large_droplet(precision=0, nz=16384, nr=12288, radius=2500.0, eos=OracleEOS)
     p, rho0 = wl.params[0], wl.rho0[0]
     with lbm.LbmAxi(p, rho0, precision=0) as sim:
         sim.set_launch(width=256, seg_rows=0, persistent=0, grid=0, xcd_swizzle=1, regf=0)
